@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the block-step Hermite hot path on one MI355X.
+
+Workload: King W0=7 cluster, N = 2^20 equal-mass stars (Henon units,
+eps = 1e-4), 6th-order Hermite.  One step is one full pass of the hot path --
+block-step scheduler, predictor over all N, pairwise force on the active
+set, corrector + interpolation + time step -- with every particle on one
+level (k_min = k_max = 10), so each step has N_act = N and does N_act * N =
+2^40 pair interactions (self pair counted).  Metric: pair interactions per
+second of the whole step, MIXED force precision, with the FP64 force timed
+beside it and the error of both against the CPU oracle on a sample of rows.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s & % VALU peak, 6th-order N=1M, mixed vs FP64 at stated error"
+# Algorithmic flops per pair interaction (minimal operation list of the
+# pairwise force with potential; add/sub/mul = 1, FMA = 2, rsqrt = 1):
+FLOPS_PER_INTERACTION = {4: 43, 6: 80, 8: 127}
+# The count commonly quoted for Hermite N-body codes (weights rsqrt heavier):
+FLOPS_LITERATURE = {4: 60, 6: 97, 8: 144}
+# Chip peak of the VALU for the instruction mix this build can issue: 256 CUs
+# x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.  This is both the FP64
+# vector peak and the FP32 peak without packed (two-wide) FP32 instructions,
+# which the build does not emit; the packed-FP32 figure is 157.3.
+PEAK_VALU_TFLOPS = 78.6
+PEAK_PACKED_FP32_TFLOPS = 157.3
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "force_mixed_p6_n1M_traffic.md")
+FORCE_SOURCES = [os.path.join(ROOT, "paper_1312_1789_amd", "csrc", f) for f in ("force.hip", "records.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n_act: int, n: int):
+    """HBM bytes per force launch from the committed counter summary, or None
+    when it is missing or was taken on a different force-kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    vals = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("force_source_sha") != source_digest():
+        return None
+    if int(vals.get("n", -1)) != n or int(vals.get("n_act", -1)) != n_act:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_precision(model, precision, order, steps, warmup, level):
+    import torch
+    from paper_1312_1789_amd import Simulation
+    sim = Simulation(model.m, model.x, model.v, order=order, precision=precision, eps2=1e-8, eta=0.1,
+                     eta_start=0.01, k_min=level, k_max=level)
+    t0 = time.perf_counter()
+    sim.init()
+    torch.cuda.synchronize()
+    log("[%s] init (two FP64 force passes) %.2f s" % (precision, time.perf_counter() - t0))
+    for w in range(warmup):
+        t, na = sim.step()
+        log("[%s] warmup step %d: tick %d n_act %d" % (precision, w, t, na))
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_act_sum = 0
+    for k in range(steps):
+        t, na = sim.step()
+        n_act_sum += na
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases, nt = sim.timers()
+    ms_step = wall / steps * 1e3
+    inter = float(n_act_sum) * model.n
+    log("[%s] %d steps: %.1f ms/step, %.4e interactions/s; phases (ms/step) %s"
+        % (precision, steps, ms_step, inter / wall, {k: round(v / nt, 3) for k, v in phases.items()}))
+    return sim, {"ms_per_step": ms_step, "interactions_per_s": inter / wall, "n_act_per_step": n_act_sum / steps,
+                 "phase_ms_per_step": {k: v / nt for k, v in phases.items()}}
+
+
+def cpu_baseline_and_error(model, sims, order, target_s):
+    """The oracle on the host cores: force on a bounded sample of active rows
+    of the same step (the state of the MIXED run, predicted to its next
+    time), timed; and the error of each GPU precision on those rows."""
+    import torch
+    import oracle
+    import nbody_ics
+    from oracle import OracleConfig
+    n = model.n
+    sim = sims["mixed"]
+    h = sim.to_numpy()
+    T = int((h["t_tick"] + (1 << (20 - h["level"].astype(np.int64)))).min())
+    cfg = OracleConfig(order=order, eps2=1e-8)
+    st = oracle.State(h["m"], h["x"], h["v"], order, h["d"], h["t_tick"], h["level"])
+    xp, vp, ap, jp = oracle.predict(cfg, st, T)
+    # calibrate the sample size on 128 rows
+    cal = nbody_ics.active_subset(n, 128, 1500)
+    t0 = time.perf_counter()
+    oracle.force(cfg, h["m"], xp, vp, ap, None, act=cal)
+    rate = 128 * n / (time.perf_counter() - t0)
+    rows = int(min(max(256, target_s * rate / n), 65536)) // 64 * 64
+    sample = nbody_ics.active_subset(n, rows, 1500 + 12)
+    t0 = time.perf_counter()
+    ref = oracle.force(cfg, h["m"], xp, vp, ap, None, act=sample)
+    dt = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    log("[cpu] oracle: %d rows x %d j in %.1f s on %d threads = %.3e interactions/s" % (rows, n, dt, cores,
+                                                                                      rows * n / dt))
+    errors = {}
+    act = torch.as_tensor(sample, device="cuda:0")
+    for prec, s in sims.items():
+        s.load_state(h["x"], h["v"], h["d"], h["t_tick"], h["level"])
+        s.predict(T)
+        out = s.force_block(act)
+        torch.cuda.synchronize()
+        e = {}
+        for key in ("acc", "jrk", "snp"):
+            g = out[key].cpu().numpy()
+            r = np.linalg.norm(g - ref[key], axis=0) / np.linalg.norm(ref[key], axis=0)
+            e[key] = {"rms": float(np.sqrt(np.mean(r * r))), "max": float(r.max())}
+        errors[prec] = e
+        log("[cpu] %s error vs oracle: %s" % (prec, {k: "%.2e/%.2e" % (v["rms"], v["max"]) for k, v in e.items()}))
+    base = {"value": rows * n / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "sample": "%d random active rows x all %d j-particles of the same 6th-order step (FP64 C oracle, "
+                      "OpenMP over rows), %.1f s" % (rows, n, dt)}
+    return base, errors, rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--order", type=int, default=6)
+    ap.add_argument("--level", type=int, default=10, help="shared block level (dt = 2^-level)")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import nbody_ics
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1312_1789_amd import abi
+    abi.lib()
+
+    t0 = time.perf_counter()
+    model = nbody_ics.king(args.n, 7.0, 13)
+    log("workload: King W0=7 n=%d (%.1f s to generate)" % (args.n, time.perf_counter() - t0))
+
+    sims, res = {}, {}
+    for prec, k in (("mixed", args.steps), ("fp64", args.fp64_steps or args.steps)):
+        sims[prec], res[prec] = run_precision(model, prec, args.order, k, args.warmup, args.level)
+
+    n = args.n
+    mixed = res["mixed"]
+    force_ms = mixed["phase_ms_per_step"]["force"]
+    n_act = int(round(mixed["n_act_per_step"]))
+    flops_launch = FLOPS_PER_INTERACTION[args.order] * float(n_act) * n
+    achieved = flops_launch / (force_ms * 1e-3) / 1e12
+    traffic = read_traffic(n_act, n)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_force<PolMx<6>> (MIXED 6th-order pairwise force)",
+                "flops_per_interaction": FLOPS_PER_INTERACTION[args.order],
+                "force_ms_per_launch": round(force_ms, 3),
+                "frac_of_packed_fp32_peak": round(achieved / PEAK_PACKED_FP32_TFLOPS, 4)}
+
+    cpu, errors, rows = None, None, 0
+    if not args.no_cpu_baseline:
+        cpu, errors, rows = cpu_baseline_and_error(model, sims, args.order, args.cpu_seconds)
+
+    fp64 = res["fp64"]
+    fp64_force_ms = fp64["phase_ms_per_step"]["force"]
+    line = {
+        "metric": METRIC,
+        "value": mixed["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "King W0=7 cluster, n=%d, 6th-order Hermite block step with all n particles "
+                               "active (one shared level k=%d), MIXED pairwise force" % (n, args.level),
+                   "n": n, "order": args.order, "precision": "mixed", "n_act": n_act, "eps": 1e-4,
+                   "interactions_per_step": float(n_act) * n, "interaction_count": "n_act * n (self pair counted)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "force_only": {"mixed_interactions_per_s": float(n_act) * n / (force_ms * 1e-3),
+                       "fp64_interactions_per_s": float(n_act) * n / (fp64_force_ms * 1e-3),
+                       "mixed_over_fp64": fp64_force_ms / force_ms,
+                       "mixed_gflops_80": achieved * 1e3,
+                       "mixed_gflops_97": FLOPS_LITERATURE[args.order] * float(n_act) * n / (force_ms * 1e-3) / 1e9},
+        "fp64": {"value": fp64["interactions_per_s"], "ms_per_step": fp64["ms_per_step"],
+                 "phase_ms_per_step": fp64["phase_ms_per_step"]},
+        "phase_ms_per_step": mixed["phase_ms_per_step"],
+        "error_vs_oracle": errors,
+        "error_rows": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

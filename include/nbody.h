@@ -1,0 +1,193 @@
+/*
+ * nbody.h -- C-ABI of the MI355X (gfx950) block-step Hermite N-body hot path.
+ *
+ * The method (paper: Abstract; Sec. "Codes description"): direct summation of
+ * softened Newtonian gravity between all particles, integrated with a
+ * 4th-, 6th- or 8th-order Hermite predictor-corrector scheme and individual
+ * hierarchical (power-of-two) block time steps, with the force evaluated in
+ * mixed FP32/FP64 precision (paper: Fig. 1 and Fig. 5 captions, "mixed
+ * (fp32 + fp64) precision").  The paper names the scheme without formulas;
+ * the library follows the standard published ones: the force-derivative
+ * recursion, corrector and generalised time-step criterion of Nitadori &
+ * Makino (2008), and Aarseth's criterion for order 4.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers owned by the caller, unless the
+ *    comment says "host".  The library never allocates device memory: the
+ *    caller passes one workspace at create time.
+ *  - 3-vector arrays are component-major [3][len]: the x components of all
+ *    elements, then the y components, then the z components.
+ *  - Time is an integer tick count of 2^-20 time units.  A particle on level k
+ *    (k_min <= k <= k_max <= 20) has dt = 2^-k = 2^(20-k) ticks; its time is
+ *    always a multiple of its dt.
+ *  - Work is enqueued on the HIP stream given to nbody_create.  Entry points
+ *    that return host values (n_act, t_next, energies) synchronise that
+ *    stream; the others are asynchronous.
+ *  - Errors come back as a negative nbody_status; nbody_last_error() gives a
+ *    message (thread-local).  Nothing aborts or throws across the ABI.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NBODY_OK = 0,
+    NBODY_E_INVALID = -1,     /* bad argument: null / misaligned pointer, bad size or option */
+    NBODY_E_HIP = -2,         /* a HIP runtime call failed */
+    NBODY_E_WORKSPACE = -3,   /* workspace missing, too small or not 256-byte aligned */
+    NBODY_E_STATE = -4,       /* call out of order (e.g. force before any predict) */
+    NBODY_E_UNSUPPORTED = -5, /* option not supported on this device / build */
+    NBODY_E_NONFINITE = -6    /* a corrected value was NaN or infinite */
+} nbody_status;
+
+/* Arithmetic of the pairwise force (the corrector, time step, predictor and
+ * energy are FP64 in every mode). */
+typedef enum {
+    NBODY_FP64 = 0,  /* all FP64 */
+    NBODY_MIXED = 1, /* FP64 position / velocity differences, FP32 rsqrt and
+                        pairwise arithmetic, FP32 partial sums over j-chunks of
+                        at most 64 terms added into FP64 accumulators */
+    NBODY_DS = 2     /* FP32-only hardware: double-single (hi + lo float)
+                        positions and velocities, FP32 arithmetic, compensated
+                        (two-sum) double-single accumulation of every term */
+} nbody_precision;
+
+typedef struct {
+    int32_t order;      /* Hermite order: 4, 6 or 8 */
+    int32_t precision;  /* nbody_precision */
+    int64_t n;          /* number of particles, 2 <= n <= 2^26 */
+    int64_t n_hard;     /* pairs with BOTH indices < n_hard are unsoftened (eps = 0); 0 <= n_hard <= n */
+    double eps2;        /* softening length squared for all other pairs, >= 0;
+                           eps2 == 0 makes every pair unsoftened */
+    double eta;         /* time-step accuracy parameter (inside the square root for order 4,
+                           outside the power for orders 6 and 8) */
+    double eta_start;   /* initial step: dt0 = eta_start |a| / |jerk| */
+    int32_t k_min;      /* largest step 2^-k_min */
+    int32_t k_max;      /* smallest step 2^-k_max, k_min <= k_max <= 20 */
+} nbody_config;
+
+/* Particle state, DEVICE pointers, caller-owned, 8-byte aligned.
+ * m[n]; x, v [3][n]; d[k] = k-th derivative of the acceleration a^(k), [3][n],
+ * for k = 0 .. order-3 (a, jerk; + snap, crackle for order >= 6; + a^(4), a^(5)
+ * for order 8), unused entries NULL; t_tick[n] particle times; level[n]. */
+typedef struct {
+    double *m;
+    double *x;
+    double *v;
+    double *d[6];
+    int64_t *t_tick;
+    int32_t *level;
+} nbody_state;
+
+/* Counters kept by a context since creation (host copy). */
+typedef struct {
+    int64_t steps;          /* block steps taken by nbody_step */
+    int64_t sum_n_act;      /* sum of n_act over those steps */
+    double interactions;    /* sum of n_act * n over force evaluations */
+    int64_t dt_underflow;   /* corrected particles whose dt_crit was below 2^-k_max */
+    int64_t nonfinite;      /* corrected particles with a non-finite value */
+} nbody_stats;
+
+typedef struct nbody_ctx nbody_ctx;
+
+/* Bytes of device workspace a context for this configuration needs. */
+nbody_status nbody_workspace_size(const nbody_config *cfg, size_t *bytes /* host */);
+
+/* Create a context.  workspace: DEVICE memory of at least
+ * nbody_workspace_size() bytes, 256-byte aligned, owned by the caller and kept
+ * alive until nbody_destroy.  stream: a hipStream_t (NULL = default stream).
+ * *out (host) receives the context. */
+nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes, void *stream,
+                          nbody_ctx **out);
+nbody_status nbody_destroy(nbody_ctx *ctx);
+
+/* Initial forces and steps at t = 0 (all particles): acceleration and jerk
+ * from (x, v); snap and crackle from a second FP64 pass that uses them; for
+ * order 8, a^(4) = a^(5) = 0.  Sets t_tick = 0 and each level from
+ * dt0 = eta_start |a|/|jerk| (largest 2^-k <= dt0, clamped to [k_min, k_max]).
+ * Reads m, x, v; writes d[], t_tick, level. */
+nbody_status nbody_init(nbody_ctx *ctx, nbody_state *state);
+
+/* Predict every particle to time t_tick (Taylor series of its stored
+ * derivatives about its own time: x to dt^(p-1), v to dt^(p-2), a to dt^(p-3),
+ * jerk to dt^(p-4)) into the context's j-particle records, which
+ * nbody_force_block reads.  t_tick must be >= every particle's time. */
+nbody_status nbody_predict(nbody_ctx *ctx, const nbody_state *state, int64_t t_tick);
+
+/* Force and derivatives on the active particles act_idx[0 .. n_act) from
+ * the predicted records of the last nbody_predict: for each active i, the sum
+ * over all j != i of the softened pairwise acceleration, jerk, snap (order
+ * >= 6), crackle (order 8) and potential -m_j / sqrt(r^2 + eps_ij^2).
+ * act_idx: int32 indices in [0, n), no duplicates (order free).
+ * Outputs [3][n_act] (pot: [n_act]) FP64, row q belongs to act_idx[q].
+ * snp / crk may be NULL when the order does not define them; pot may be
+ * NULL.  The j-sum order is fixed, so reruns are bitwise identical. */
+nbody_status nbody_force_block(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, double *acc,
+                               double *jrk, double *snp, double *crk, double *pot);
+
+/* Hermite corrector, interpolated higher derivatives and new time step for
+ * the active particles, whose next time must be t_tick: x, v and d[] are
+ * overwritten with their values at t_tick, t_tick[i] = t_tick, level[i] the
+ * new level.  acc .. crk are the force outputs at t_tick ([3][n_act] as from
+ * nbody_force_block; only the first order/2 are read). */
+nbody_status nbody_correct(nbody_ctx *ctx, nbody_state *state, int64_t n_act, const int32_t *act_idx,
+                           int64_t t_tick, const double *acc, const double *jrk, const double *snp,
+                           const double *crk);
+
+/* Block-step selection: t_next = min_i (t_i + dt_i); act_idx_out (DEVICE,
+ * room for n) receives the active set {i : t_i + dt_i == t_next} in
+ * increasing order.  *t_next_out, *n_act_out (host) receive the results. */
+nbody_status nbody_schedule(nbody_ctx *ctx, const nbody_state *state, int32_t *act_idx_out,
+                            int64_t *t_next_out, int64_t *n_act_out);
+
+/* One whole block step: schedule, predict all, force on the active set,
+ * correct.  *t_tick_out / *n_act_out (host, may be NULL) receive the new time
+ * and the number of particles advanced.  Returns NBODY_E_NONFINITE when a
+ * corrected value became NaN or infinite. */
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *state, int64_t *t_tick_out, int64_t *n_act_out);
+
+/* FP64 energy of the state (meaningful when all particles share one time):
+ * *ekin = sum m v^2 / 2, *epot = - sum_{i<j} m_i m_j / sqrt(r^2 + eps_ij^2).
+ * Host outputs; fixed summation order. */
+nbody_status nbody_energy(nbody_ctx *ctx, const nbody_state *state, double *ekin, double *epot);
+
+/* Copy the predicted records of the last nbody_predict out as FP64 arrays
+ * [3][n] (DEVICE pointers): position, velocity, and for order >= 6 the
+ * acceleration, order 8 the jerk (ap / jp may be NULL).  In MIXED and DS mode
+ * these are the values the force kernel sees (FP32 acceleration / jerk,
+ * double-single hi + lo sums). */
+nbody_status nbody_get_predicted(nbody_ctx *ctx, double *xp, double *vp, double *ap, double *jp);
+
+/* Counters since creation (host output). */
+nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
+
+/* Launch shape of the force kernel: ni = active particles per lane (1 or 2),
+ * block = threads per workgroup (64, 128 or 256), n_split = j-range splits
+ * (0 = chosen per call from n_act).  Results do not depend on ni or block;
+ * they depend on n_split only through the FP64 summation order. */
+nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split);
+
+/* Phase timers of nbody_step, measured with HIP events on the context's
+ * stream.  nbody_set_timing(ctx, 1) creates the events and starts
+ * accumulating; 0 stops.  nbody_get_timers writes, in milliseconds summed over
+ * the timed steps: [0] scheduler, [1] host round trip between scheduling and
+ * prediction, [2] predictor, [3] force (pairwise kernel and split reduction),
+ * [4] corrector + time step; *steps (host) = number of timed steps. */
+nbody_status nbody_set_timing(nbody_ctx *ctx, int32_t enable);
+nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5] /* host */, int64_t *steps /* host */);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *nbody_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -1,0 +1,200 @@
+"""ctypes binding of libnbody.so: the entry points of include/nbody.h under
+the same names, with argument marshalling only (every step of the path runs
+in the HIP kernels).  Device pointers are plain integers (e.g. a torch
+tensor's ``data_ptr()``); the stream is a ``hipStream_t`` integer.
+
+Loading fails loudly when the library has not been built: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbody.so")
+
+NBODY_OK = 0
+NBODY_E_INVALID = -1
+NBODY_E_HIP = -2
+NBODY_E_WORKSPACE = -3
+NBODY_E_STATE = -4
+NBODY_E_UNSUPPORTED = -5
+NBODY_E_NONFINITE = -6
+
+NBODY_FP64 = 0
+NBODY_MIXED = 1
+NBODY_DS = 2
+PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED, "ds": NBODY_DS}
+
+#: every symbol the header declares
+EXPORTS = (
+    "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
+    "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_energy",
+    "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
+    "nbody_last_error",
+)
+
+
+class nbody_config(C.Structure):
+    _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("n", C.c_int64), ("n_hard", C.c_int64),
+                ("eps2", C.c_double), ("eta", C.c_double), ("eta_start", C.c_double),
+                ("k_min", C.c_int32), ("k_max", C.c_int32)]
+
+
+class nbody_state(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("x", C.c_void_p), ("v", C.c_void_p), ("d", C.c_void_p * 6),
+                ("t_tick", C.c_void_p), ("level", C.c_void_p)]
+
+
+class nbody_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("sum_n_act", C.c_int64), ("interactions", C.c_double),
+                ("dt_underflow", C.c_int64), ("nonfinite", C.c_int64)]
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (func, status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnbody.so is not built (%s); run paper_1312_1789_amd/build_lib.py" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        I64 = C.c_int64
+        sig = {
+            "nbody_workspace_size": [C.POINTER(nbody_config), C.POINTER(C.c_size_t)],
+            "nbody_create": [C.POINTER(nbody_config), P, C.c_size_t, P, C.POINTER(P)],
+            "nbody_destroy": [P],
+            "nbody_init": [P, C.POINTER(nbody_state)],
+            "nbody_predict": [P, C.POINTER(nbody_state), I64],
+            "nbody_force_block": [P, I64, P, P, P, P, P, P],
+            "nbody_correct": [P, C.POINTER(nbody_state), I64, P, I64, P, P, P, P],
+            "nbody_schedule": [P, C.POINTER(nbody_state), P, C.POINTER(I64), C.POINTER(I64)],
+            "nbody_step": [P, C.POINTER(nbody_state), C.POINTER(I64), C.POINTER(I64)],
+            "nbody_energy": [P, C.POINTER(nbody_state), C.POINTER(C.c_double), C.POINTER(C.c_double)],
+            "nbody_get_predicted": [P, P, P, P, P],
+            "nbody_get_stats": [P, C.POINTER(nbody_stats)],
+            "nbody_set_launch": [P, C.c_int32, C.c_int32, C.c_int32],
+            "nbody_set_timing": [P, C.c_int32],
+            "nbody_get_timers": [P, C.POINTER(C.c_double), C.POINTER(I64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.nbody_last_error.argtypes = []
+        L.nbody_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().nbody_last_error().decode()
+
+
+def _check(status: int, func: str) -> int:
+    if status != NBODY_OK:
+        raise NBodyError(status, func, last_error())
+    return status
+
+
+def nbody_workspace_size(cfg: nbody_config) -> int:
+    b = C.c_size_t(0)
+    _check(lib().nbody_workspace_size(C.byref(cfg), C.byref(b)), "nbody_workspace_size")
+    return int(b.value)
+
+
+def nbody_create(cfg: nbody_config, workspace: int, nbytes: int, stream: int = 0) -> int:
+    out = C.c_void_p(0)
+    _check(lib().nbody_create(C.byref(cfg), C.c_void_p(workspace), nbytes, C.c_void_p(stream), C.byref(out)),
+           "nbody_create")
+    return int(out.value)
+
+
+def nbody_destroy(ctx: int) -> None:
+    _check(lib().nbody_destroy(C.c_void_p(ctx)), "nbody_destroy")
+
+
+def nbody_init(ctx: int, st: nbody_state) -> None:
+    _check(lib().nbody_init(C.c_void_p(ctx), C.byref(st)), "nbody_init")
+
+
+def nbody_predict(ctx: int, st: nbody_state, t_tick: int) -> None:
+    _check(lib().nbody_predict(C.c_void_p(ctx), C.byref(st), int(t_tick)), "nbody_predict")
+
+
+def nbody_force_block(ctx: int, n_act: int, act_idx: int, acc: int, jrk: int, snp: int = 0, crk: int = 0,
+                      pot: int = 0) -> None:
+    P = C.c_void_p
+    _check(lib().nbody_force_block(P(ctx), int(n_act), P(act_idx), P(acc), P(jrk), P(snp or None),
+                                   P(crk or None), P(pot or None)), "nbody_force_block")
+
+
+def nbody_correct(ctx: int, st: nbody_state, n_act: int, act_idx: int, t_tick: int, acc: int, jrk: int,
+                  snp: int = 0, crk: int = 0) -> None:
+    P = C.c_void_p
+    _check(lib().nbody_correct(P(ctx), C.byref(st), int(n_act), P(act_idx), int(t_tick), P(acc), P(jrk),
+                               P(snp or None), P(crk or None)), "nbody_correct")
+
+
+def nbody_schedule(ctx: int, st: nbody_state, act_idx_out: int):
+    t = C.c_int64(0)
+    na = C.c_int64(0)
+    _check(lib().nbody_schedule(C.c_void_p(ctx), C.byref(st), C.c_void_p(act_idx_out), C.byref(t), C.byref(na)),
+           "nbody_schedule")
+    return int(t.value), int(na.value)
+
+
+def nbody_step(ctx: int, st: nbody_state):
+    """One block step; returns (t_tick, n_act).  Raises NBodyError (status
+    NBODY_E_NONFINITE) when a corrected value became non-finite."""
+    t = C.c_int64(0)
+    na = C.c_int64(0)
+    _check(lib().nbody_step(C.c_void_p(ctx), C.byref(st), C.byref(t), C.byref(na)), "nbody_step")
+    return int(t.value), int(na.value)
+
+
+def nbody_energy(ctx: int, st: nbody_state):
+    T = C.c_double(0)
+    W = C.c_double(0)
+    _check(lib().nbody_energy(C.c_void_p(ctx), C.byref(st), C.byref(T), C.byref(W)), "nbody_energy")
+    return float(T.value), float(W.value)
+
+
+def nbody_get_predicted(ctx: int, xp: int, vp: int, ap: int = 0, jp: int = 0) -> None:
+    P = C.c_void_p
+    _check(lib().nbody_get_predicted(P(ctx), P(xp), P(vp), P(ap or None), P(jp or None)), "nbody_get_predicted")
+
+
+def nbody_get_stats(ctx: int) -> nbody_stats:
+    s = nbody_stats()
+    _check(lib().nbody_get_stats(C.c_void_p(ctx), C.byref(s)), "nbody_get_stats")
+    return s
+
+
+def nbody_set_launch(ctx: int, ni: int, block: int, n_split: int) -> None:
+    _check(lib().nbody_set_launch(C.c_void_p(ctx), int(ni), int(block), int(n_split)), "nbody_set_launch")
+
+
+def nbody_set_timing(ctx: int, enable: bool) -> None:
+    _check(lib().nbody_set_timing(C.c_void_p(ctx), 1 if enable else 0), "nbody_set_timing")
+
+
+PHASES = ("schedule", "host_roundtrip", "predict", "force", "correct")
+
+
+def nbody_get_timers(ctx: int):
+    """(dict phase -> total ms, number of timed steps)."""
+    ms = (C.c_double * 5)()
+    steps = C.c_int64(0)
+    _check(lib().nbody_get_timers(C.c_void_p(ctx), ms, C.byref(steps)), "nbody_get_timers")
+    return dict(zip(PHASES, list(ms))), int(steps.value)

@@ -1,0 +1,408 @@
+// api.cpp -- the C-ABI of the library: argument checks, workspace layout,
+// and the order of kernel launches for each entry point.  All device memory
+// comes from the caller (one workspace per context); the library never
+// allocates on the device.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+nbody_status fail(nbody_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define NB_HIP(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail(NBODY_E_HIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+nbody_status check_config(const nbody_config *c)
+{
+    if (!c) return fail(NBODY_E_INVALID, "config is NULL");
+    if (c->order != 4 && c->order != 6 && c->order != 8)
+        return fail(NBODY_E_INVALID, "order must be 4, 6 or 8 (got %d)", c->order);
+    if (c->precision < NBODY_FP64 || c->precision > NBODY_DS)
+        return fail(NBODY_E_INVALID, "precision must be 0 (FP64), 1 (MIXED) or 2 (DS) (got %d)", c->precision);
+    if (c->n < 2 || c->n > (int64_t(1) << 26)) return fail(NBODY_E_INVALID, "n must be in [2, 2^26] (got %lld)", (long long)c->n);
+    if (c->n_hard < 0 || c->n_hard > c->n) return fail(NBODY_E_INVALID, "n_hard must be in [0, n]");
+    if (!(c->eps2 >= 0.0) || !std::isfinite(c->eps2)) return fail(NBODY_E_INVALID, "eps2 must be finite and >= 0");
+    if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return fail(NBODY_E_INVALID, "eta must be > 0");
+    if (!(c->eta_start > 0.0) || !std::isfinite(c->eta_start)) return fail(NBODY_E_INVALID, "eta_start must be > 0");
+    if (c->k_min < 0 || c->k_min > c->k_max || c->k_max > nb::kLevelMax)
+        return fail(NBODY_E_INVALID, "need 0 <= k_min <= k_max <= 20 (got %d, %d)", c->k_min, c->k_max);
+    return NBODY_OK;
+}
+
+nbody_status check_state(const nbody_ctx *ctx, const nbody_state *st)
+{
+    if (!st) return fail(NBODY_E_INVALID, "state is NULL");
+    const void *ptrs[] = {st->m, st->x, st->v, st->t_tick, st->level};
+    for (const void *p : ptrs)
+        if (!p || !aligned8(p)) return fail(NBODY_E_INVALID, "state pointers must be non-NULL and 8-byte aligned");
+    for (int k = 0; k <= ctx->cfg.order - 3; ++k)
+        if (!st->d[k] || !aligned8(st->d[k]))
+            return fail(NBODY_E_INVALID, "state d[%d] must be non-NULL and 8-byte aligned for order %d", k, ctx->cfg.order);
+    return NBODY_OK;
+}
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class T> T *ws_at(nbody_ctx *ctx, size_t off) { return reinterpret_cast<T *>(ctx->ws + off); }
+
+nb::DevScalars *scalars(nbody_ctx *ctx) { return ws_at<nb::DevScalars>(ctx, ctx->lay.scal); }
+
+int64_t hard_count(const nbody_config &c) { return c.eps2 == 0.0 ? c.n : c.n_hard; }
+
+nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec, int64_t n_act,
+                       const int32_t *act, double *acc, double *jrk, double *snp, double *crk, double *pot)
+{
+    nb::ForceArgs a{};
+    a.rec = rec;
+    a.n = ctx->cfg.n;
+    a.act = act;
+    a.n_act = n_act;
+    a.eps2 = ctx->cfg.eps2;
+    a.n_hard = hard_count(ctx->cfg);
+    a.out[0] = acc;
+    a.out[1] = jrk;
+    a.out[2] = snp;
+    a.out[3] = crk;
+    a.out[4] = pot;
+    a.part = ws_at<double>(ctx, ctx->lay.part);
+    a.ni = ctx->ni;
+    a.block = ctx->block;
+    a.n_split = ctx->n_split;
+    int used = 0;
+    NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
+    ctx->stats.interactions += double(n_act) * double(ctx->cfg.n);
+    return NBODY_OK;
+}
+
+nbody_status read_scalars(nbody_ctx *ctx, nb::DevScalars *h)
+{
+    NB_HIP(hipMemcpyAsync(h, scalars(ctx), sizeof(*h), hipMemcpyDeviceToHost, ctx->stream));
+    NB_HIP(hipStreamSynchronize(ctx->stream));
+    return NBODY_OK;
+}
+
+}  // namespace
+
+namespace nb {
+
+Layout make_layout(const nbody_config &c)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += up256(bytes);
+        return at;
+    };
+    const size_t n = size_t(c.n);
+    const size_t nb = (n + kSchedChunk - 1) / kSchedChunk;
+    L.rec = take(n * size_t(record_bytes(c.order, c.precision)));
+    L.part = take(size_t(kPartEntries) * kMaxComp * sizeof(double));
+    L.force = take(12 * n * sizeof(double));
+    L.act = take(n * sizeof(int32_t));
+    L.sched = take(nb * (2 * sizeof(int64_t) + sizeof(int32_t)));
+    L.scal = take(sizeof(DevScalars));
+    L.energy = take(2 * ((n + 255) / 256) * sizeof(double));
+    L.init = 0;
+    L.irec = take(n * 112);
+    L.total = off;
+    return L;
+}
+
+}  // namespace nb
+
+extern "C" {
+
+const char *nbody_last_error(void) { return g_err; }
+
+nbody_status nbody_workspace_size(const nbody_config *cfg, size_t *bytes)
+{
+    nbody_status s = check_config(cfg);
+    if (s != NBODY_OK) return s;
+    if (!bytes) return fail(NBODY_E_INVALID, "bytes is NULL");
+    *bytes = nb::make_layout(*cfg).total;
+    return NBODY_OK;
+}
+
+nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes, void *stream, nbody_ctx **out)
+{
+    nbody_status s = check_config(cfg);
+    if (s != NBODY_OK) return s;
+    if (!out) return fail(NBODY_E_INVALID, "out is NULL");
+    const nb::Layout L = nb::make_layout(*cfg);
+    if (!workspace) return fail(NBODY_E_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) return fail(NBODY_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < L.total) return fail(NBODY_E_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, L.total);
+    nbody_ctx *ctx = new (std::nothrow) nbody_ctx();
+    if (!ctx) return fail(NBODY_E_INVALID, "out of host memory");
+    ctx->cfg = *cfg;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->ws = static_cast<char *>(workspace);
+    ctx->ws_bytes = bytes;
+    ctx->lay = L;
+    ctx->predicted = false;
+    ctx->ni = 1;
+    ctx->block = 256;
+    ctx->n_split = 0;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e == hipSuccess) e = hipMemsetAsync(scalars(ctx), 0, sizeof(nb::DevScalars), ctx->stream);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(NBODY_E_HIP, "nbody_create: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return NBODY_OK;
+}
+
+nbody_status nbody_destroy(nbody_ctx *ctx)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (ctx->ev_made)
+        for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    delete ctx;
+    return NBODY_OK;
+}
+
+nbody_status nbody_set_timing(nbody_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (enable && !ctx->ev_made) {
+        for (hipEvent_t &e : ctx->ev) NB_HIP(hipEventCreate(&e));
+        ctx->ev_made = true;
+    }
+    ctx->timing = enable != 0;
+    return NBODY_OK;
+}
+
+nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5], int64_t *steps)
+{
+    if (!ctx || !ms) return fail(NBODY_E_INVALID, "ctx and ms are required");
+    for (int k = 0; k < 5; ++k) ms[k] = ctx->phase_ms[k];
+    if (steps) *steps = ctx->timed_steps;
+    return NBODY_OK;
+}
+
+nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (ni != 1 && ni != 2) return fail(NBODY_E_INVALID, "ni must be 1 or 2");
+    if (block != 64 && block != 128 && block != 256) return fail(NBODY_E_INVALID, "block must be 64, 128 or 256");
+    if (n_split < 0 || n_split > 65535) return fail(NBODY_E_INVALID, "n_split must be in [0, 65535]");
+    ctx->ni = ni;
+    ctx->block = block;
+    ctx->n_split = n_split;
+    return NBODY_OK;
+}
+
+nbody_status nbody_init(nbody_ctx *ctx, nbody_state *st)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    const nbody_config &c = ctx->cfg;
+    void *irec = ctx->ws + ctx->lay.irec;
+    int32_t *all = ws_at<int32_t>(ctx, ctx->lay.act);
+    NB_HIP(nb::launch_iota(c.n, all, ctx->stream));
+    // pass 1: acceleration and jerk from positions and velocities
+    NB_HIP(nb::launch_pack_f64(c.n, st->m, st->x, st->v, nullptr, nullptr, irec, ctx->stream));
+    s = run_force(ctx, 8, NBODY_FP64, irec, c.n, all, st->d[0], st->d[1], nullptr, nullptr, nullptr);
+    if (s != NBODY_OK) return s;
+    if (c.order >= 6) {
+        // pass 2: snap and crackle, using the pass-1 acceleration and jerk
+        NB_HIP(nb::launch_pack_f64(c.n, st->m, st->x, st->v, st->d[0], st->d[1], irec, ctx->stream));
+        s = run_force(ctx, 8, NBODY_FP64, irec, c.n, all, nullptr, nullptr, st->d[2], st->d[3], nullptr);
+        if (s != NBODY_OK) return s;
+    }
+    NB_HIP(nb::launch_init_levels(c, *st, st->d[0], st->d[1], ctx->stream));
+    ctx->predicted = false;
+    return NBODY_OK;
+}
+
+nbody_status nbody_predict(nbody_ctx *ctx, const nbody_state *st, int64_t t_tick)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (t_tick < 0) return fail(NBODY_E_INVALID, "t_tick must be >= 0");
+    NB_HIP(nb::launch_predict(ctx->cfg.order, ctx->cfg.precision, ctx->cfg.n, *st, t_tick, ctx->ws + ctx->lay.rec,
+                              ctx->stream));
+    ctx->predicted = true;
+    return NBODY_OK;
+}
+
+nbody_status nbody_force_block(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, double *acc, double *jrk,
+                               double *snp, double *crk, double *pot)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (!ctx->predicted) return fail(NBODY_E_STATE, "nbody_force_block before nbody_predict");
+    if (n_act < 0 || n_act > ctx->cfg.n) return fail(NBODY_E_INVALID, "n_act must be in [0, n]");
+    if (n_act == 0) return NBODY_OK;
+    if (!act_idx || (reinterpret_cast<uintptr_t>(act_idx) & 3u)) return fail(NBODY_E_INVALID, "act_idx must be non-NULL, 4-byte aligned");
+    if (!acc || !jrk || !aligned8(acc) || !aligned8(jrk)) return fail(NBODY_E_INVALID, "acc and jrk must be non-NULL, 8-byte aligned");
+    const double *opt[3] = {snp, crk, pot};
+    for (const double *p : opt)
+        if (p && !aligned8(p)) return fail(NBODY_E_INVALID, "outputs must be 8-byte aligned");
+    if (ctx->cfg.order < 6) snp = nullptr;
+    if (ctx->cfg.order < 8) crk = nullptr;
+    return run_force(ctx, ctx->cfg.order, ctx->cfg.precision, ctx->ws + ctx->lay.rec, n_act, act_idx, acc, jrk, snp,
+                     crk, pot);
+}
+
+nbody_status nbody_correct(nbody_ctx *ctx, nbody_state *st, int64_t n_act, const int32_t *act_idx, int64_t t_tick,
+                           const double *acc, const double *jrk, const double *snp, const double *crk)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (n_act < 0 || n_act > ctx->cfg.n) return fail(NBODY_E_INVALID, "n_act must be in [0, n]");
+    if (n_act == 0) return NBODY_OK;
+    if (!act_idx) return fail(NBODY_E_INVALID, "act_idx is NULL");
+    if (!acc || !jrk) return fail(NBODY_E_INVALID, "acc and jrk are required");
+    if (ctx->cfg.order >= 6 && !snp) return fail(NBODY_E_INVALID, "snp is required for order >= 6");
+    if (ctx->cfg.order >= 8 && !crk) return fail(NBODY_E_INVALID, "crk is required for order 8");
+    const double *f[4] = {acc, jrk, snp, crk};
+    NB_HIP(nb::launch_correct(ctx->cfg, *st, n_act, act_idx, nullptr, t_tick, f, scalars(ctx), ctx->stream));
+    return NBODY_OK;
+}
+
+nbody_status nbody_schedule(nbody_ctx *ctx, const nbody_state *st, int32_t *act_idx_out, int64_t *t_next_out,
+                            int64_t *n_act_out)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (!act_idx_out) return fail(NBODY_E_INVALID, "act_idx_out is NULL");
+    NB_HIP(nb::launch_schedule(ctx->cfg.n, st->t_tick, st->level, ctx->ws + ctx->lay.sched, act_idx_out,
+                               scalars(ctx), ctx->stream));
+    nb::DevScalars h;
+    s = read_scalars(ctx, &h);
+    if (s != NBODY_OK) return s;
+    if (t_next_out) *t_next_out = h.t_next;
+    if (n_act_out) *n_act_out = h.n_act;
+    return NBODY_OK;
+}
+
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int64_t *t_tick_out, int64_t *n_act_out)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    const nbody_config &c = ctx->cfg;
+    int32_t *act = ws_at<int32_t>(ctx, ctx->lay.act);
+    int64_t t_next = 0, n_act = 0;
+    const bool tm = ctx->timing && ctx->ev_made;
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+    NB_HIP(nb::launch_schedule(c.n, st->t_tick, st->level, ctx->ws + ctx->lay.sched, act, scalars(ctx),
+                               ctx->stream));
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+    nb::DevScalars h;
+    s = read_scalars(ctx, &h);
+    if (s != NBODY_OK) return s;
+    t_next = h.t_next;
+    n_act = h.n_act;
+    if (n_act <= 0 || n_act > c.n) return fail(NBODY_E_STATE, "scheduler found %lld active particles", (long long)n_act);
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+    s = nbody_predict(ctx, st, t_next);
+    if (s != NBODY_OK) return s;
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+    double *F = ws_at<double>(ctx, ctx->lay.force);
+    double *acc = F, *jrk = F + 3 * n_act, *snp = F + 6 * n_act, *crk = F + 9 * n_act;
+    s = run_force(ctx, c.order, c.precision, ctx->ws + ctx->lay.rec, n_act, act, acc, jrk,
+                  c.order >= 6 ? snp : nullptr, c.order >= 8 ? crk : nullptr, nullptr);
+    if (s != NBODY_OK) return s;
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+    const double *f[4] = {acc, jrk, snp, crk};
+    NB_HIP(nb::launch_correct(c, *st, n_act, act, nullptr, t_next, f, scalars(ctx), ctx->stream));
+    if (tm) NB_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+    ctx->stats.steps += 1;
+    ctx->stats.sum_n_act += n_act;
+    s = read_scalars(ctx, &h);
+    if (s != NBODY_OK) return s;
+    if (tm) {
+        for (int k = 0; k < 5; ++k) {
+            float ms = 0.0f;
+            NB_HIP(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+            ctx->phase_ms[k] += ms;
+        }
+        ctx->timed_steps += 1;
+    }
+    const int64_t nonfinite_before = ctx->stats.nonfinite;
+    ctx->stats.dt_underflow = int64_t(h.underflow);
+    ctx->stats.nonfinite = int64_t(h.nonfinite);
+    if (t_tick_out) *t_tick_out = t_next;
+    if (n_act_out) *n_act_out = n_act;
+    if (ctx->stats.nonfinite > nonfinite_before)
+        return fail(NBODY_E_NONFINITE, "%lld corrected particles became non-finite at tick %lld",
+                    (long long)(ctx->stats.nonfinite - nonfinite_before), (long long)t_next);
+    return NBODY_OK;
+}
+
+nbody_status nbody_energy(nbody_ctx *ctx, const nbody_state *st, double *ekin, double *epot)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (!ekin || !epot) return fail(NBODY_E_INVALID, "ekin and epot are required");
+    int np = 0;
+    double *part = ws_at<double>(ctx, ctx->lay.energy);
+    NB_HIP(nb::launch_energy(ctx->cfg.n, hard_count(ctx->cfg), ctx->cfg.eps2, st->m, st->x, st->v, part, &np,
+                             ctx->stream));
+    std::vector<double> h(2 * size_t(np));
+    NB_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    NB_HIP(hipStreamSynchronize(ctx->stream));
+    double T = 0.0, W = 0.0;
+    for (int b = 0; b < np; ++b) {
+        T += h[2 * b];
+        W += h[2 * b + 1];
+    }
+    *ekin = T;
+    *epot = W;
+    return NBODY_OK;
+}
+
+nbody_status nbody_get_predicted(nbody_ctx *ctx, double *xp, double *vp, double *ap, double *jp)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (!ctx->predicted) return fail(NBODY_E_STATE, "nbody_get_predicted before nbody_predict");
+    if (!xp || !vp || !aligned8(xp) || !aligned8(vp)) return fail(NBODY_E_INVALID, "xp and vp must be non-NULL, 8-byte aligned");
+    if (ctx->cfg.order < 6) ap = nullptr;
+    if (ctx->cfg.order < 8) jp = nullptr;
+    NB_HIP(nb::launch_unpack(ctx->cfg.order, ctx->cfg.precision, ctx->cfg.n, ctx->ws + ctx->lay.rec, xp, vp, ap, jp,
+                             ctx->stream));
+    return NBODY_OK;
+}
+
+nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out)
+{
+    if (!ctx || !out) return fail(NBODY_E_INVALID, "ctx and out are required");
+    nb::DevScalars h;
+    nbody_status s = read_scalars(ctx, &h);
+    if (s != NBODY_OK) return s;
+    ctx->stats.dt_underflow = int64_t(h.underflow);
+    ctx->stats.nonfinite = int64_t(h.nonfinite);
+    *out = ctx->stats;
+    return NBODY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,600 @@
+// integrate.hip -- the O(n) and O(n_act) kernels of a block step on gfx950:
+// block-step scheduler, predictor, Hermite corrector with interpolation and
+// time step, initial levels, and the FP64 energy diagnostic.
+//
+// Method (paper: Abstract; Sec. "Codes description"): Hermite integration of
+// order 4, 6 or 8 with individual hierarchical block time steps.  Formulas:
+// time-symmetric Hermite corrector (order 4: Hut & Makino; orders 6 and 8:
+// Nitadori & Makino 2008), derivatives at the end of the step from the
+// Hermite interpolant through both ends, Aarseth's step criterion (order 4)
+// and its generalisation (orders 6 and 8, Nitadori & Makino 2008).
+#include <climits>
+
+#include "internal.h"
+#include "records.h"
+
+namespace nb {
+namespace {
+
+// --------------------------------------------------------------------------
+// Predictor: Taylor series about each particle's own time to t, in Horner
+// form.  D[0..p-1] = x, v, a, jerk, ...; returns sum_k D[k] dt^k / k!.
+template <int N>
+__device__ __forceinline__ double taylor(const double *D, double dt)
+{
+    double s = D[N - 1];
+#pragma unroll
+    for (int k = N - 1; k >= 1; --k) s = __builtin_fma(s, dt * (1.0 / double(k)), D[k - 1]);
+    return s;
+}
+
+template <int P, int PREC>
+__global__ void __launch_bounds__(256)
+k_predict(int64_t n, const double *__restrict__ m, const double *__restrict__ x, const double *__restrict__ v,
+          const double *__restrict__ d0, const double *__restrict__ d1, const double *__restrict__ d2,
+          const double *__restrict__ d3, const double *__restrict__ d4, const double *__restrict__ d5,
+          const int64_t *__restrict__ t_tick, int64_t t, void *__restrict__ rec_out)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = double(t - t_tick[i]) * (1.0 / double(kTicksPerUnit));
+    const double *ds[6] = {d0, d1, d2, d3, d4, d5};
+    double xp[3], vp[3], ap[3], jp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double D[P];
+        D[0] = x[c * n + i];
+        D[1] = v[c * n + i];
+#pragma unroll
+        for (int k = 0; k < P - 2; ++k) D[k + 2] = ds[k][c * n + i];
+        xp[c] = taylor<P>(D, dt);
+        vp[c] = taylor<P - 1>(D + 1, dt);
+        if constexpr (P >= 6) ap[c] = taylor<P - 2>(D + 2, dt);
+        if constexpr (P >= 8) jp[c] = taylor<P - 3>(D + 3, dt);
+    }
+    const double mi = m[i];
+    if constexpr (PREC == NBODY_FP64) {
+        RecF64<P> r{};
+        r.x = xp[0]; r.y = xp[1]; r.z = xp[2]; r.m = mi;
+        r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
+        if constexpr (P >= 6) { r.ax = ap[0]; r.ay = ap[1]; r.az = ap[2]; }
+        if constexpr (P >= 8) { r.jx = jp[0]; r.jy = jp[1]; r.jz = jp[2]; }
+        static_cast<RecF64<P> *>(rec_out)[i] = r;
+    } else if constexpr (PREC == NBODY_MIXED) {
+        RecMx<P> r{};
+        r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
+        r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
+        r.m = float(mi);
+        if constexpr (P >= 6) { r.ax = float(ap[0]); r.ay = float(ap[1]); r.az = float(ap[2]); }
+        if constexpr (P >= 8) { r.jx = float(jp[0]); r.jy = float(jp[1]); r.jz = float(jp[2]); }
+        static_cast<RecMx<P> *>(rec_out)[i] = r;
+    } else {
+        RecDS<P> r{};
+        float hx[3], lx[3], hv[3], lv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hx[c] = float(xp[c]);
+            lx[c] = float(xp[c] - double(hx[c]));
+            hv[c] = float(vp[c]);
+            lv[c] = float(vp[c] - double(hv[c]));
+        }
+        r.xh = hx[0]; r.yh = hx[1]; r.zh = hx[2]; r.m = float(mi);
+        r.xl = lx[0]; r.yl = lx[1]; r.zl = lx[2];
+        r.vxh = hv[0]; r.vyh = hv[1]; r.vzh = hv[2];
+        r.vxl = lv[0]; r.vyl = lv[1]; r.vzl = lv[2];
+        if constexpr (P >= 6) { r.ax = float(ap[0]); r.ay = float(ap[1]); r.az = float(ap[2]); }
+        if constexpr (P >= 8) { r.jx = float(jp[0]); r.jy = float(jp[1]); r.jz = float(jp[2]); }
+        static_cast<RecDS<P> *>(rec_out)[i] = r;
+    }
+}
+
+// Predicted records back to FP64 arrays [3][n] (inspection and tests).
+template <int P, int PREC>
+__global__ void __launch_bounds__(256)
+k_unpack(int64_t n, const void *__restrict__ rec, double *__restrict__ xp, double *__restrict__ vp,
+         double *__restrict__ ap, double *__restrict__ jp)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double X[3], V[3], A[3] = {0, 0, 0}, J[3] = {0, 0, 0};
+    if constexpr (PREC == NBODY_FP64) {
+        const RecF64<P> r = static_cast<const RecF64<P> *>(rec)[i];
+        X[0] = r.x; X[1] = r.y; X[2] = r.z; V[0] = r.vx; V[1] = r.vy; V[2] = r.vz;
+        if constexpr (P >= 6) { A[0] = r.ax; A[1] = r.ay; A[2] = r.az; }
+        if constexpr (P >= 8) { J[0] = r.jx; J[1] = r.jy; J[2] = r.jz; }
+    } else if constexpr (PREC == NBODY_MIXED) {
+        const RecMx<P> r = static_cast<const RecMx<P> *>(rec)[i];
+        X[0] = r.x; X[1] = r.y; X[2] = r.z; V[0] = r.vx; V[1] = r.vy; V[2] = r.vz;
+        if constexpr (P >= 6) { A[0] = r.ax; A[1] = r.ay; A[2] = r.az; }
+        if constexpr (P >= 8) { J[0] = r.jx; J[1] = r.jy; J[2] = r.jz; }
+    } else {
+        const RecDS<P> r = static_cast<const RecDS<P> *>(rec)[i];
+        X[0] = double(r.xh) + double(r.xl); X[1] = double(r.yh) + double(r.yl); X[2] = double(r.zh) + double(r.zl);
+        V[0] = double(r.vxh) + double(r.vxl); V[1] = double(r.vyh) + double(r.vyl); V[2] = double(r.vzh) + double(r.vzl);
+        if constexpr (P >= 6) { A[0] = r.ax; A[1] = r.ay; A[2] = r.az; }
+        if constexpr (P >= 8) { J[0] = r.jx; J[1] = r.jy; J[2] = r.jz; }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xp[c * n + i] = X[c];
+        vp[c * n + i] = V[c];
+        if (ap) ap[c * n + i] = A[c];
+        if (jp) jp[c * n + i] = J[c];
+    }
+}
+
+// FP64 order-8 records from plain arrays (initialisation passes).
+__global__ void __launch_bounds__(256)
+k_pack_f64(int64_t n, const double *__restrict__ m, const double *__restrict__ x, const double *__restrict__ v,
+           const double *__restrict__ a, const double *__restrict__ j, RecF64<8> *__restrict__ rec)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    RecF64<8> r{};
+    r.x = x[i]; r.y = x[n + i]; r.z = x[2 * n + i]; r.m = m[i];
+    r.vx = v[i]; r.vy = v[n + i]; r.vz = v[2 * n + i];
+    if (a) { r.ax = a[i]; r.ay = a[n + i]; r.az = a[2 * n + i]; }
+    if (j) { r.jx = j[i]; r.jy = j[n + i]; r.jz = j[2 * n + i]; }
+    rec[i] = r;
+}
+
+// --------------------------------------------------------------------------
+// Time-step level.  Largest 2^-k <= dt, i.e. k = -floor(log2 dt), clamped to
+// [k_min, k_max]; NaN or zero gives k_max.
+__device__ __forceinline__ int level_for(double dt, int k_min, int k_max)
+{
+    if (!(dt > 0.0)) return k_max;
+    if (dt >= ldexp(1.0, -k_min)) return k_min;
+    int k = -ilogb(dt);
+    if (k < k_min) k = k_min;
+    if (k > k_max) k = k_max;
+    return k;
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c)
+{
+    return __builtin_sqrt(__builtin_fma(a, a, __builtin_fma(b, b, c * c)));
+}
+
+// Integer coefficients of the Hermite interpolant's derivatives at the end of
+// a step of length h, with scaled inputs P_k = a^(k)(t0) h^k and
+// Q_k = a^(k)(t1) h^k (k < p/2):  a^(m)(t1) h^m = sum_k CP[m][k] P_k + CQ[m][k] Q_k.
+// (Derived by solving the confluent interpolation conditions symbolically.)
+__constant__ double kCP4[2][2] = {{6, 2}, {12, 6}};
+__constant__ double kCQ4[2][2] = {{-6, 4}, {-12, 6}};
+__constant__ double kCP6[3][3] = {{-60, -24, -3}, {-360, -168, -24}, {-720, -360, -60}};
+__constant__ double kCQ6[3][3] = {{60, -36, 9}, {360, -192, 36}, {720, -360, 60}};
+__constant__ double kCP8[4][4] = {{840, 360, 60, 4}, {10080, 4680, 840, 60}, {50400, 24480, 4680, 360},
+                                  {100800, 50400, 10080, 840}};
+__constant__ double kCQ8[4][4] = {{-840, 480, -120, 16}, {-10080, 5400, -1200, 120}, {-50400, 25920, -5400, 480},
+                                  {-100800, 50400, -10080, 840}};
+
+template <int P>
+__device__ __forceinline__ double interp(int m, const double *Ps, const double *Qs)
+{
+    constexpr int q = P / 2;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < q; ++k) {
+        double cp, cq;
+        if constexpr (P == 4) { cp = kCP4[m][k]; cq = kCQ4[m][k]; }
+        else if constexpr (P == 6) { cp = kCP6[m][k]; cq = kCQ6[m][k]; }
+        else { cp = kCP8[m][k]; cq = kCQ8[m][k]; }
+        s = __builtin_fma(cp, Ps[k], __builtin_fma(cq, Qs[k], s));
+    }
+    return s;
+}
+
+// Corrector + interpolation + new step for the active particles.
+template <int P>
+__global__ void __launch_bounds__(256)
+k_correct(int64_t n, int64_t n_act_host, const int32_t *__restrict__ act, const DevScalars *src,
+          int64_t t1_host, double *__restrict__ x, double *__restrict__ v, double *__restrict__ d0,
+          double *__restrict__ d1, double *__restrict__ d2, double *__restrict__ d3, double *__restrict__ d4,
+          double *__restrict__ d5, int64_t *__restrict__ t_tick, int32_t *__restrict__ level,
+          const double *__restrict__ f0, const double *__restrict__ f1, const double *__restrict__ f2,
+          const double *__restrict__ f3, double eta, int k_min, int k_max, DevScalars *sc)
+{
+    constexpr int q = P / 2;
+    // active count and end time from the host, or from the device scheduler
+    const int64_t qi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t na = src ? src->n_act : n_act_host;
+    if (qi >= na) return;
+    const int64_t t1 = src ? src->t_next : t1_host;
+    const int64_t i = act[qi];
+    if (i < 0 || i >= n) return;   // an index outside [0, n) is ignored
+    const double h = double(t1 - t_tick[i]) * (1.0 / double(kTicksPerUnit));
+    double *dst[6] = {d0, d1, d2, d3, d4, d5};
+    const double *fnew[4] = {f0, f1, f2, f3};
+    double all[P][3];   // a^(0..p-1) at t1
+    double xn[3], vn[3];
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double A0[q], A1[q];
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            A0[k] = dst[k][c * n + i];
+            A1[k] = fnew[k][c * na + qi];
+        }
+        const double x0 = x[c * n + i], v0 = v[c * n + i];
+        // velocity: integral of the interpolant of a(t); position: the same
+        // quadrature applied to v(t) with the corrected end velocity
+        double v1, x1;
+        if constexpr (P == 4) {
+            v1 = v0 + h * __builtin_fma(h, (A0[1] - A1[1]) * (1.0 / 12.0), 0.5 * (A0[0] + A1[0]));
+            x1 = x0 + h * __builtin_fma(h, (A0[0] - A1[0]) * (1.0 / 12.0), 0.5 * (v0 + v1));
+        } else if constexpr (P == 6) {
+            v1 = v0 + h * __builtin_fma(h, __builtin_fma(h, (A0[2] + A1[2]) * (1.0 / 120.0),
+                                                          (A0[1] - A1[1]) * (1.0 / 10.0)),
+                                        0.5 * (A0[0] + A1[0]));
+            x1 = x0 + h * __builtin_fma(h, __builtin_fma(h, (A0[1] + A1[1]) * (1.0 / 120.0),
+                                                          (A0[0] - A1[0]) * (1.0 / 10.0)),
+                                        0.5 * (v0 + v1));
+        } else {
+            v1 = v0 + h * __builtin_fma(h, __builtin_fma(h, __builtin_fma(h, (A0[3] - A1[3]) * (1.0 / 1680.0),
+                                                                          (A0[2] + A1[2]) * (1.0 / 84.0)),
+                                                          (A0[1] - A1[1]) * (3.0 / 28.0)),
+                                        0.5 * (A0[0] + A1[0]));
+            x1 = x0 + h * __builtin_fma(h, __builtin_fma(h, __builtin_fma(h, (A0[2] - A1[2]) * (1.0 / 1680.0),
+                                                                          (A0[1] + A1[1]) * (1.0 / 84.0)),
+                                                          (A0[0] - A1[0]) * (3.0 / 28.0)),
+                                        0.5 * (v0 + v1));
+        }
+        xn[c] = x1;
+        vn[c] = v1;
+        finite = finite && __builtin_isfinite(x1) && __builtin_isfinite(v1);
+        // higher derivatives at t1 from the interpolant
+        double Ps[q], Qs[q];
+        double hk = 1.0;
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            Ps[k] = A0[k] * hk;
+            Qs[k] = A1[k] * hk;
+            all[k][c] = A1[k];
+            hk *= h;
+        }
+#pragma unroll
+        for (int m = 0; m < q; ++m) {
+            all[q + m][c] = interp<P>(m, Ps, Qs) / hk;
+            hk *= h;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c * n + i] = xn[c];
+        v[c * n + i] = vn[c];
+#pragma unroll
+        for (int k = 0; k <= P - 3; ++k) dst[k][c * n + i] = all[k][c];
+    }
+    double F[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) F[k] = norm3(all[k][0], all[k][1], all[k][2]);
+    double dtc;
+    if constexpr (P == 4) {
+        dtc = __builtin_sqrt(eta * __builtin_fma(F[0], F[2], F[1] * F[1]) / __builtin_fma(F[1], F[3], F[2] * F[2]));
+    } else {
+        const double a1 = __builtin_sqrt(F[0] * F[2]) + F[1];
+        const double ak = __builtin_sqrt(F[P - 3] * F[P - 1]) + F[P - 2];
+        dtc = (P == 6) ? eta * cbrt(a1 / ak) : eta * pow(a1 / ak, 0.2);
+    }
+    const int old = level[i];
+    int k = level_for(dtc, k_min, k_max);
+    if (k < old) {
+        const int kd = old - 1;
+        const int64_t dt2 = int64_t(1) << (kLevelMax - kd);
+        k = (kd >= k_min && (t1 % dt2) == 0) ? kd : old;
+    }
+    level[i] = k;
+    t_tick[i] = t1;
+    if (!(dtc >= ldexp(1.0, -k_max))) atomicAdd(&sc->underflow, 1ull);
+    if (!finite) atomicAdd(&sc->nonfinite, 1ull);
+}
+
+// Initial levels from dt0 = eta_start |a| / |jerk|; times zero.
+__global__ void __launch_bounds__(256)
+k_init_levels(int64_t n, const double *__restrict__ a, const double *__restrict__ j, double eta_start, int k_min,
+              int k_max, int64_t *__restrict__ t_tick, int32_t *__restrict__ level)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double am = norm3(a[i], a[n + i], a[2 * n + i]);
+    const double jm = norm3(j[i], j[n + i], j[2 * n + i]);
+    level[i] = level_for(eta_start * am / jm, k_min, k_max);
+    t_tick[i] = 0;
+}
+
+// --------------------------------------------------------------------------
+// Scheduler.  Pass 1: per-block minimum of t_i + dt_i.  Pass 2: every block
+// reduces the block minima to t_next and counts its active particles.
+// Pass 3 (one block): exclusive scan of the counts, n_act.  Pass 4: each block
+// writes its active indices in increasing order at its offset.
+__device__ __forceinline__ int64_t next_time(const int64_t *t_tick, const int32_t *level, int64_t i)
+{
+    return t_tick[i] + (int64_t(1) << (kLevelMax - level[i]));
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_min(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+            int64_t *__restrict__ bmin)
+{
+    __shared__ int64_t sm[kSchedBlock];
+    const int64_t base = int64_t(blockIdx.x) * kSchedChunk;
+    int64_t mn = INT64_MAX;
+#pragma unroll
+    for (int k = 0; k < kSchedPerThread; ++k) {
+        const int64_t i = base + int64_t(k) * kSchedBlock + threadIdx.x;
+        if (i < n) {
+            const int64_t tn = next_time(t_tick, level, i);
+            mn = tn < mn ? tn : mn;
+        }
+    }
+    sm[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) sm[threadIdx.x] = sm[threadIdx.x + s] < sm[threadIdx.x] ? sm[threadIdx.x + s] : sm[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmin[blockIdx.x] = sm[0];
+}
+
+__device__ __forceinline__ int64_t block_min_all(const int64_t *bmin, int nb, int64_t *sm)
+{
+    int64_t mn = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
+    sm[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) sm[threadIdx.x] = sm[threadIdx.x + s] < sm[threadIdx.x] ? sm[threadIdx.x + s] : sm[threadIdx.x];
+        __syncthreads();
+    }
+    const int64_t r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_count(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+              const int64_t *__restrict__ bmin, int nb, int32_t *__restrict__ bcnt, DevScalars *__restrict__ sc)
+{
+    __shared__ int64_t sm[kSchedBlock];
+    __shared__ int cnt[kSchedBlock];
+    const int64_t tn = block_min_all(bmin, nb, sm);
+    const int64_t base = int64_t(blockIdx.x) * kSchedChunk;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kSchedPerThread; ++k) {
+        const int64_t i = base + int64_t(k) * kSchedBlock + threadIdx.x;
+        if (i < n && next_time(t_tick, level, i) == tn) ++c;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bcnt[blockIdx.x] = cnt[0];
+        if (blockIdx.x == 0) sc->t_next = tn;
+    }
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ boff, DevScalars *__restrict__ sc)
+{
+    // one block: sequential chunks of kSchedBlock, scanned in LDS
+    __shared__ int64_t s[kSchedBlock];
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kSchedBlock) {
+        const int b = b0 + threadIdx.x;
+        const int64_t v = b < nb ? bcnt[b] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kSchedBlock; o <<= 1) {
+            const int64_t add = int(threadIdx.x) >= o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (b < nb) boff[b] = carry + s[threadIdx.x] - v;
+        carry += s[kSchedBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->n_act = carry;
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_compact(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+                const int64_t *__restrict__ boff, const DevScalars *__restrict__ sc, int32_t *__restrict__ act)
+{
+    __shared__ int s[kSchedBlock];
+    const int64_t tn = sc->t_next;
+    const int64_t base = int64_t(blockIdx.x) * kSchedChunk + int64_t(threadIdx.x) * kSchedPerThread;
+    int flags[kSchedPerThread];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kSchedPerThread; ++k) {
+        const int64_t i = base + k;
+        flags[k] = (i < n && next_time(t_tick, level, i) == tn) ? 1 : 0;
+        c += flags[k];
+    }
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < kSchedBlock; o <<= 1) {
+        const int add = int(threadIdx.x) >= o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t pos = boff[blockIdx.x] + s[threadIdx.x] - c;
+#pragma unroll
+    for (int k = 0; k < kSchedPerThread; ++k)
+        if (flags[k]) act[pos++] = int32_t(base + k);
+}
+
+// --------------------------------------------------------------------------
+// FP64 energy: per block, sum over its i of m_i v_i^2 and of
+// m_i sum_{j != i} m_j / sqrt(r_ij^2 + eps_ij^2); fixed-order tree in LDS.
+__global__ void __launch_bounds__(256)
+k_energy(int64_t n, int64_t n_hard, double eps2, const double *__restrict__ m, const double *__restrict__ x,
+         const double *__restrict__ v, double *__restrict__ partial)
+{
+    __shared__ double sk[256], sw[256];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t ii = i < n ? i : n - 1;
+    const double xi = x[ii], yi = x[n + ii], zi = x[2 * n + ii];
+    double w = 0.0;
+    const int64_t jh = n_hard < n ? n_hard : n;
+    for (int64_t j = 0; j < jh; ++j) {
+        const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
+        const double e = ii < n_hard ? 0.0 : eps2;
+        double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e)));
+        const bool ok = j != ii;
+        r2 = ok ? r2 : 1.0;
+        w += ok ? m[j] * rsqrt64(r2) : 0.0;
+    }
+    for (int64_t j = jh; j < n; ++j) {
+        const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+        w += m[j] * rsqrt64(r2);
+    }
+    if (ii >= jh) w -= m[ii] * rsqrt64(eps2);   // self pair of the softened loop
+    const double vx = v[ii], vy = v[n + ii], vz = v[2 * n + ii];
+    sk[threadIdx.x] = i < n ? m[ii] * __builtin_fma(vx, vx, __builtin_fma(vy, vy, vz * vz)) : 0.0;
+    sw[threadIdx.x] = i < n ? m[ii] * w : 0.0;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) {
+            sk[threadIdx.x] += sk[threadIdx.x + s];
+            sw[threadIdx.x] += sw[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = 0.5 * sk[0];
+        partial[2 * blockIdx.x + 1] = -0.5 * sw[0];
+    }
+}
+
+__global__ void k_iota(int64_t n, int32_t *__restrict__ a)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = int32_t(i);
+}
+
+__global__ void k_fill(int64_t n, double *__restrict__ a, double val)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = val;
+}
+
+unsigned blocks_for(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+template <int P>
+hipError_t predict_p(int precision, int64_t n, const nbody_state &st, int64_t t, void *rec, hipStream_t s)
+{
+    const unsigned g = blocks_for(n, 256);
+#define NB_PRED(PREC)                                                                                           \
+    hipLaunchKernelGGL((k_predict<P, PREC>), dim3(g), dim3(256), 0, s, n, st.m, st.x, st.v, st.d[0], st.d[1],  \
+                       st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, t, rec)
+    if (precision == NBODY_MIXED) NB_PRED(NBODY_MIXED);
+    else if (precision == NBODY_DS) NB_PRED(NBODY_DS);
+    else NB_PRED(NBODY_FP64);
+#undef NB_PRED
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_predict(int order, int precision, int64_t n, const nbody_state &st, int64_t t_tick, void *rec,
+                          hipStream_t s)
+{
+    if (order == 4) return predict_p<4>(precision, n, st, t_tick, rec, s);
+    if (order == 6) return predict_p<6>(precision, n, st, t_tick, rec, s);
+    return predict_p<8>(precision, n, st, t_tick, rec, s);
+}
+
+hipError_t launch_unpack(int order, int precision, int64_t n, const void *rec, double *xp, double *vp, double *ap,
+                         double *jp, hipStream_t s)
+{
+    const unsigned g = blocks_for(n, 256);
+#define NB_UNP(P, PREC) hipLaunchKernelGGL((k_unpack<P, PREC>), dim3(g), dim3(256), 0, s, n, rec, xp, vp, ap, jp)
+#define NB_UNP_P(P)                                                   \
+    if (precision == NBODY_MIXED) NB_UNP(P, NBODY_MIXED);             \
+    else if (precision == NBODY_DS) NB_UNP(P, NBODY_DS);              \
+    else NB_UNP(P, NBODY_FP64)
+    if (order == 4) { NB_UNP_P(4); }
+    else if (order == 6) { NB_UNP_P(6); }
+    else { NB_UNP_P(8); }
+#undef NB_UNP_P
+#undef NB_UNP
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f64(int64_t n, const double *m, const double *x, const double *v, const double *a,
+                           const double *j, void *rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, m, x, v, a, j,
+                       static_cast<RecF64<8> *>(rec));
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t n_act, const int32_t *act,
+                          const DevScalars *src, int64_t t_tick_host, const double *const f[4],
+                          DevScalars *sc, hipStream_t s)
+{
+    const unsigned g = blocks_for(n_act, 256);   // n_act: exact, or an upper bound when src is set
+    if (g == 0) return hipSuccess;
+#define NB_CORR(P)                                                                                             \
+    hipLaunchKernelGGL((k_correct<P>), dim3(g), dim3(256), 0, s, c.n, n_act, act, src, t_tick_host,            \
+                       st.x, st.v, st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, st.level, \
+                       f[0], f[1], f[2], f[3], c.eta, int(c.k_min), int(c.k_max), sc)
+    if (c.order == 4) NB_CORR(4);
+    else if (c.order == 6) NB_CORR(6);
+    else NB_CORR(8);
+#undef NB_CORR
+    return hipGetLastError();
+}
+
+hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *level, void *scratch,
+                           int32_t *act_out, DevScalars *sc, hipStream_t s)
+{
+    const int nb = int((n + kSchedChunk - 1) / kSchedChunk);
+    int64_t *bmin = static_cast<int64_t *>(scratch);
+    int64_t *boff = bmin + nb;
+    int32_t *bcnt = reinterpret_cast<int32_t *>(boff + nb);
+    hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin);
+    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, nb, bcnt, sc);
+    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bcnt, nb, boff, sc);
+    hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, boff, sc, act_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_levels(const nbody_config &c, const nbody_state &st, const double *a, const double *j,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_levels, dim3(blocks_for(c.n, 256)), dim3(256), 0, s, c.n, a, j, c.eta_start,
+                       int(c.k_min), int(c.k_max), st.t_tick, st.level);
+    if (c.order == 8) {
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(3 * c.n, 256)), dim3(256), 0, s, 3 * c.n, st.d[4], 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(3 * c.n, 256)), dim3(256), 0, s, 3 * c.n, st.d[5], 0.0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(int64_t n, int64_t n_hard, double eps2, const double *m, const double *x,
+                         const double *v, double *partials, int *n_partials, hipStream_t s)
+{
+    const unsigned g = blocks_for(n, 256);
+    *n_partials = int(g);
+    hipLaunchKernelGGL(k_energy, dim3(g), dim3(256), 0, s, n, n_hard, eps2, m, x, v, partials);
+    return hipGetLastError();
+}
+
+}  // namespace nb

@@ -1,0 +1,111 @@
+// internal.h -- shared definitions of the gfx950 N-body library (not part of
+// the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "nbody.h"
+
+namespace nb {
+
+constexpr int kLevelMax = 20;               // time tick = 2^-20 time units
+constexpr int64_t kTicksPerUnit = int64_t(1) << kLevelMax;
+constexpr int kSchedBlock = 256;            // threads per scheduler block
+constexpr int kSchedPerThread = 4;          // particles per scheduler thread
+constexpr int kSchedChunk = kSchedBlock * kSchedPerThread;
+constexpr int kMixedChunk = 64;             // FP32 partial-sum length in MIXED mode
+constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act_pad * n_split)
+constexpr int kMaxComp = 13;                // acc3 + jerk3 + snap3 + crackle3 + pot
+
+// Components of a force result for a Hermite order: 3 per derivative + pot.
+inline int n_comp(int order) { return 3 * (order / 2) + 1; }
+
+// Bytes of one predicted j-particle record.
+int record_bytes(int order, int precision);
+
+// Offsets of the sub-buffers inside the caller's workspace (bytes).
+struct Layout {
+    size_t rec;        // predicted records, n * record_bytes
+    size_t part;       // j-split partial sums, kPartEntries * kMaxComp doubles
+    size_t force;      // step force outputs, kMaxComp-1 rows of n doubles ([12][n])
+    size_t act;        // active indices, n int32
+    size_t sched;      // scheduler per-block scratch (min ticks, counts, offsets)
+    size_t scal;       // device scalars: t_next, n_act, counters
+    size_t energy;     // energy partials
+    size_t init;       // init scratch: 4 x [3][n] doubles (a, j, s, c of the two passes)
+    size_t irec;       // init records (FP64 order-8 layout), n * 112
+    size_t total;
+};
+Layout make_layout(const nbody_config &c);
+
+// Device scalars at Layout::scal.
+struct DevScalars {
+    int64_t t_next;
+    int64_t n_act;
+    unsigned long long underflow;
+    unsigned long long nonfinite;
+    int64_t pad[4];
+};
+
+// Force launch request.
+struct ForceArgs {
+    const void *rec;        // predicted records
+    int64_t n;
+    const int32_t *act;
+    int64_t n_act;
+    double eps2;
+    int64_t n_hard;         // already n when eps2 == 0
+    double *out[5];         // acc, jrk, snp, crk, pot ([3][n_act] / [n_act]); may be null
+    double *part;           // partial-sum scratch
+    int ni, block, n_split; // launch shape (n_split 0 = auto)
+};
+
+hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split);
+
+// Pack FP64 order-8 records {x, m, v, a, j} from state arrays (a, j may be null = 0).
+hipError_t launch_pack_f64(int64_t n, const double *m, const double *x, const double *v, const double *a,
+                           const double *j, void *rec, hipStream_t s);
+
+hipError_t launch_predict(int order, int precision, int64_t n, const nbody_state &st, int64_t t_tick,
+                          void *rec, hipStream_t s);
+
+// Corrector for act[0..n_act); when src is non-null the count and the end
+// time are read from it on the device (n_act is then an upper bound).
+hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t n_act, const int32_t *act,
+                          const DevScalars *src, int64_t t_tick_host, const double *const f[4],
+                          DevScalars *sc, hipStream_t s);
+
+hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s);
+
+hipError_t launch_unpack(int order, int precision, int64_t n, const void *rec, double *xp, double *vp, double *ap,
+                         double *jp, hipStream_t s);
+
+hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *level, void *sched_scratch,
+                           int32_t *act_out, DevScalars *sc, hipStream_t s);
+
+hipError_t launch_init_levels(const nbody_config &c, const nbody_state &st, const double *a, const double *j,
+                              hipStream_t s);
+
+hipError_t launch_energy(int64_t n, int64_t n_hard, double eps2, const double *m, const double *x,
+                         const double *v, double *partials, int *n_partials, hipStream_t s);
+
+}  // namespace nb
+
+struct nbody_ctx {
+    nbody_config cfg;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    nb::Layout lay;
+    int device;
+    bool predicted;
+    int ni, block, n_split;
+    nbody_stats stats;
+    bool timing;              // record phase events in nbody_step
+    hipEvent_t ev[6];         // phase boundaries (created on first enable)
+    bool ev_made;
+    double phase_ms[5];
+    int64_t timed_steps;
+};

@@ -1,0 +1,151 @@
+"""Thin Python front end over the C-ABI: device memory and streams come from
+PyTorch (ROCm build), every computation from libnbody.so.
+
+    sim = Simulation(m, x, v, order=6, precision="mixed", eps2=1e-8)
+    sim.init()
+    t, n_act = sim.step()
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def _dev(a, dtype, device):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
+
+
+class Simulation:
+    """Particle state, workspace and context on one GPU.
+
+    m (n,), x and v (3, n) are host arrays (copied to the device).  State
+    tensors: ``m``, ``x``, ``v`` and ``d[k]`` (k = 0 .. order-3) float64,
+    ``t_tick`` int64, ``level`` int32, component-major like the C-ABI."""
+
+    def __init__(self, m, x, v, order: int = 4, precision: str | int = "fp64", eps2: float = 1e-8,
+                 n_hard: int = 0, eta: float = 0.01, eta_start: float = 0.01, k_min: int = 3, k_max: int = 20,
+                 device: str = "cuda:0", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the N-body library runs only on the device")
+        self.device = torch.device(device)
+        self.order = int(order)
+        prec = abi.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        n = int(np.asarray(m).shape[0])
+        self.n = n
+        self.cfg = abi.nbody_config(self.order, prec, n, int(n_hard), float(eps2), float(eta), float(eta_start),
+                                    int(k_min), int(k_max))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.m = _dev(m, torch.float64, self.device)
+        self.x = _dev(np.asarray(x).reshape(3, n), torch.float64, self.device)
+        self.v = _dev(np.asarray(v).reshape(3, n), torch.float64, self.device)
+        self.d = [torch.zeros((3, n), dtype=torch.float64, device=self.device) for _ in range(self.order - 2)]
+        self.t_tick = torch.zeros(n, dtype=torch.int64, device=self.device)
+        self.level = torch.zeros(n, dtype=torch.int32, device=self.device)
+        nbytes = abi.nbody_workspace_size(self.cfg)
+        # 256-byte aligned workspace carved from a byte tensor
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.ctx = abi.nbody_create(self.cfg, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.state = self._state_struct()
+
+    def _state_struct(self) -> abi.nbody_state:
+        ds = [t.data_ptr() for t in self.d] + [None] * (6 - len(self.d))
+        return abi.nbody_state(self.m.data_ptr(), self.x.data_ptr(), self.v.data_ptr(),
+                               (abi.C.c_void_p * 6)(*ds), self.t_tick.data_ptr(), self.level.data_ptr())
+
+    def close(self):
+        if getattr(self, "ctx", 0):
+            abi.nbody_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- entry points -------------------------------------------------------
+    def set_launch(self, ni: int = 1, block: int = 256, n_split: int = 0):
+        abi.nbody_set_launch(self.ctx, ni, block, n_split)
+
+    def set_timing(self, enable: bool = True):
+        abi.nbody_set_timing(self.ctx, enable)
+
+    def timers(self):
+        return abi.nbody_get_timers(self.ctx)
+
+    def init(self):
+        abi.nbody_init(self.ctx, self.state)
+
+    def predict(self, t_tick: int):
+        abi.nbody_predict(self.ctx, self.state, t_tick)
+
+    def alloc_forces(self, n_act: int):
+        z = lambda: torch.empty((3, n_act), dtype=torch.float64, device=self.device)
+        return {"acc": z(), "jrk": z(), "snp": z(), "crk": z(),
+                "pot": torch.empty(n_act, dtype=torch.float64, device=self.device)}
+
+    def force_block(self, act: torch.Tensor, out: dict | None = None, with_pot: bool = True):
+        """Forces on the active indices (int32 device tensor) from the last
+        prediction; returns dict of (3, n_act) tensors and pot (n_act,)."""
+        n_act = int(act.numel())
+        out = out if out is not None else self.alloc_forces(n_act)
+        abi.nbody_force_block(self.ctx, n_act, act.data_ptr(), out["acc"].data_ptr(), out["jrk"].data_ptr(),
+                              out["snp"].data_ptr(), out["crk"].data_ptr(),
+                              out["pot"].data_ptr() if with_pot else 0)
+        return out
+
+    def correct(self, act: torch.Tensor, t_tick: int, f: dict):
+        abi.nbody_correct(self.ctx, self.state, int(act.numel()), act.data_ptr(), t_tick, f["acc"].data_ptr(),
+                          f["jrk"].data_ptr(), f["snp"].data_ptr(), f["crk"].data_ptr())
+
+    def predicted(self) -> dict:
+        """The last prediction as FP64 device tensors xp, vp, ap, jp (3, n)."""
+        z = lambda: torch.zeros((3, self.n), dtype=torch.float64, device=self.device)
+        out = {"xp": z(), "vp": z(), "ap": z(), "jp": z()}
+        abi.nbody_get_predicted(self.ctx, out["xp"].data_ptr(), out["vp"].data_ptr(), out["ap"].data_ptr(),
+                                out["jp"].data_ptr())
+        return out
+
+    def schedule(self):
+        act = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        t, na = abi.nbody_schedule(self.ctx, self.state, act.data_ptr())
+        return t, act[:na]
+
+    def step(self):
+        return abi.nbody_step(self.ctx, self.state)
+
+    def energy(self):
+        return abi.nbody_energy(self.ctx, self.state)
+
+    def stats(self) -> abi.nbody_stats:
+        return abi.nbody_get_stats(self.ctx)
+
+    def integrate(self, t_end_tick: int, max_steps: int = 1 << 62):
+        """Block steps until every particle reaches t_end_tick."""
+        steps = 0
+        while steps < max_steps:
+            nxt = self.t_tick + (torch.ones_like(self.t_tick) << (20 - self.level.to(torch.int64)))
+            if int(nxt.min()) > t_end_tick:
+                break
+            self.step()
+            steps += 1
+        return steps
+
+    def to_numpy(self) -> dict:
+        torch.cuda.synchronize(self.device)
+        return {"m": self.m.cpu().numpy(), "x": self.x.cpu().numpy(), "v": self.v.cpu().numpy(),
+                "d": [t.cpu().numpy() for t in self.d], "t_tick": self.t_tick.cpu().numpy(),
+                "level": self.level.cpu().numpy()}
+
+    def load_state(self, x, v, d, t_tick, level):
+        """Overwrite the device state from host arrays."""
+        self.x.copy_(_dev(np.asarray(x).reshape(3, self.n), torch.float64, self.device))
+        self.v.copy_(_dev(np.asarray(v).reshape(3, self.n), torch.float64, self.device))
+        for k, a in enumerate(d):
+            self.d[k].copy_(_dev(np.asarray(a).reshape(3, self.n), torch.float64, self.device))
+        self.t_tick.copy_(_dev(t_tick, torch.int64, self.device))
+        self.level.copy_(_dev(level, torch.int32, self.device))

@@ -1,0 +1,73 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/nbody.h declares, and validates arguments before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1312_1789_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "nbody.h")).read()
+    return sorted(set(re.findall(r"\b(nbody_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = abi.lib()
+    declared = _header_symbols()
+    assert set(declared) == set(abi.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _cfg(**kw):
+    base = dict(order=6, precision=abi.NBODY_MIXED, n=1000, n_hard=0, eps2=1e-8, eta=0.1, eta_start=0.01,
+                k_min=3, k_max=20)
+    base.update(kw)
+    return abi.nbody_config(base["order"], base["precision"], base["n"], base["n_hard"], base["eps2"],
+                            base["eta"], base["eta_start"], base["k_min"], base["k_max"])
+
+
+def test_workspace_size_scales_with_n():
+    a = abi.nbody_workspace_size(_cfg(n=1000))
+    b = abi.nbody_workspace_size(_cfg(n=100000))
+    assert b > a > 0
+    # FP64 records are larger than MIXED ones at order 6
+    assert abi.nbody_workspace_size(_cfg(precision=abi.NBODY_FP64, n=100000)) > b
+
+
+@pytest.mark.parametrize("kw", [dict(order=5), dict(order=10), dict(precision=3), dict(n=1), dict(n_hard=2000),
+                                dict(eps2=-1.0), dict(eta=0.0), dict(eta_start=-1.0), dict(k_min=5, k_max=4),
+                                dict(k_max=21), dict(eps2=float("nan"))])
+def test_config_validation(kw):
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_workspace_size(_cfg(**kw))
+    assert e.value.status == abi.NBODY_E_INVALID
+    assert abi.last_error()
+
+
+def test_create_rejects_bad_workspace():
+    cfg = _cfg()
+    n = abi.nbody_workspace_size(cfg)
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_create(cfg, 0, n)
+    assert e.value.status == abi.NBODY_E_WORKSPACE
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_create(cfg, 256 * 1000 + 8, n)       # misaligned
+    assert e.value.status == abi.NBODY_E_WORKSPACE
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_create(cfg, 256 * 1000, n - 1)       # too small
+    assert e.value.status == abi.NBODY_E_WORKSPACE
+
+
+def test_null_context_is_rejected():
+    L = abi.lib()
+    assert L.nbody_destroy(None) == abi.NBODY_E_INVALID
+    assert L.nbody_step(None, None, None, None) == abi.NBODY_E_INVALID
+    assert L.nbody_set_launch(None, 1, 256, 0) == abi.NBODY_E_INVALID
+    assert L.nbody_get_predicted(None, None, None, None, None) == abi.NBODY_E_INVALID

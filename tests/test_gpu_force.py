@@ -1,0 +1,150 @@
+"""GPU parity of the pairwise force kernels (nbody_predict + nbody_force_block)
+against the CPU oracle on identical inputs, element by element.
+
+Tolerances:
+* FP64: results differ from the oracle only by summation order and the
+  last-bit rounding of rsqrt / FMA contraction: relative error per particle
+  rms <= 1e-12, max <= 1e-9 (the max allows for particles whose jerk / snap
+  nearly cancel, where the error relative to the small sum grows).
+* MIXED and DS: rms relative error <= 2e-6 (acceleration) and <= 2e-5 (jerk),
+  the accuracy bar of the mixed-precision scheme; snap and crackle,
+  higher derivatives with more cancellation, rms <= 2e-4 / 2e-3; potential
+  rms <= 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import nbody_ics
+from helpers import TICKS, cluster_with_bh, err_stats, oracle_force, physical_derivs, random_derivs, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = {"rms": 1e-12, "max": 1e-9}
+LOW_TOL = {"acc": 2e-6, "jrk": 2e-5, "snp": 2e-4, "crk": 2e-3, "pot": 1e-6}
+KEYS = {4: ["acc", "jrk"], 6: ["acc", "jrk", "snp"], 8: ["acc", "jrk", "snp", "crk"]}
+
+
+def _sim(model, order, precision, eps2, n_hard, d, **kw):
+    from paper_1312_1789_amd import Simulation
+    sim = Simulation(model.m, model.x, model.v, order=order, precision=precision, eps2=eps2, n_hard=n_hard, **kw)
+    n = model.n
+    t0 = 5 * (TICKS >> 3)
+    sim.load_state(model.x, model.v, d[: order - 2], np.full(n, t0, np.int64), np.full(n, 3, np.int32))
+    sim.predict(t0)     # zero step: the records are the state itself
+    return sim
+
+
+def _check(out, ref, order, precision, act_n):
+    for key in KEYS[order] + ["pot"]:
+        e = rel_err(out[key].cpu().numpy()[..., :act_n], ref[key])
+        st = err_stats(e)
+        say("   %-6s %-4s rms %.2e max %.2e p99.9 %.2e" % (precision, key, st["rms"], st["max"], st["p999"]))
+        if precision == "fp64":
+            assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (key, st)
+        else:
+            assert st["rms"] <= LOW_TOL[key], (key, st)
+
+
+@pytest.fixture(scope="module")
+def small_case():
+    """King W0=7 cluster of 2998 stars + BH binary: n = 3000 (not a multiple of
+    any tile), n_hard = 2, eps = 1e-4, physical a and jerk from the oracle."""
+    model = cluster_with_bh(2998, 21)
+    eps2, n_hard = 1e-8, 2
+    a, j = physical_derivs(model.m, model.x, model.v, eps2, n_hard)
+    d = [a, j, np.zeros_like(a), np.zeros_like(a), np.zeros_like(a), np.zeros_like(a)]
+    return model, eps2, n_hard, d
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_force_parity_small(small_case, order, precision):
+    model, eps2, n_hard, d = small_case
+    n = model.n
+    say("force parity order %d %s n=%d" % (order, precision, n))
+    sim = _sim(model, order, precision, eps2, n_hard, d)
+    acts = {
+        "all": np.arange(n, dtype=np.int32),
+        "subset1000": nbody_ics.active_subset(n, 1000, 1510),
+        "bh": np.array([0], np.int32),
+        "last": np.array([n - 1], np.int32),
+        "ragged17": nbody_ics.active_subset(n, 17, 1504),
+    }
+    for name, act in acts.items():
+        say("  act=%s n_act=%d" % (name, act.size))
+        out = sim.force_block(torch.as_tensor(act, device=sim.device))
+        torch.cuda.synchronize()
+        ref = oracle_force(order, eps2, n_hard, model.m, model.x, model.v, d[0], d[1], act=act)
+        _check(out, ref, order, precision, act.size)
+
+
+def test_unsorted_active_list_permutes_rows(small_case):
+    model, eps2, n_hard, d = small_case
+    sim = _sim(model, 6, "fp64", eps2, n_hard, d)
+    act = nbody_ics.active_subset(model.n, 300, 1520)
+    perm = np.random.default_rng(0).permutation(300)
+    a1 = sim.force_block(torch.as_tensor(act, device=sim.device))["acc"].cpu().numpy()
+    a2 = sim.force_block(torch.as_tensor(act[perm], device=sim.device))["acc"].cpu().numpy()
+    np.testing.assert_array_equal(a1[:, perm], a2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_launch_shapes_and_determinism(small_case, precision):
+    """ni and block do not change any bit; reruns are bitwise identical; the
+    split count changes only the summation order (in MIXED mode also where the
+    FP32 chunk sums start, so up to FP32 rounding)."""
+    model, eps2, n_hard, d = small_case
+    sim = _sim(model, 6, precision, eps2, n_hard, d)
+    act = torch.as_tensor(nbody_ics.active_subset(model.n, 700, 1530), device=sim.device)
+    ref = None
+    for ni, block in [(1, 256), (2, 256), (1, 64), (2, 128)]:
+        sim.set_launch(ni, block, 5)
+        out = {k: t.cpu().numpy().copy() for k, t in sim.force_block(act).items()}
+        if ref is None:
+            ref = out
+        for k in ("acc", "jrk", "snp", "pot"):
+            np.testing.assert_array_equal(out[k], ref[k])
+    again = sim.force_block(act)
+    np.testing.assert_array_equal(again["acc"].cpu().numpy(), ref["acc"])
+    sim.set_launch(1, 256, 1)
+    one = sim.force_block(act)["acc"].cpu().numpy()
+    assert np.max(rel_err(one, ref["acc"])) < (1e-12 if precision == "fp64" else 1e-6)
+
+
+def test_unsoftened_pair_and_empty_call():
+    """eps = 0 (every pair unsoftened, self pair excluded by index): the
+    two-body closed form; n_act = 0 is a no-op."""
+    from paper_1312_1789_amd import Simulation
+    m = np.array([0.6, 0.4])
+    x = np.array([[0.1, -0.3], [0.2, 0.5], [-0.1, 0.0]])
+    v = np.zeros((3, 2))
+    sim = Simulation(m, x, v, order=4, precision="fp64", eps2=0.0)
+    sim.predict(0)
+    out = sim.force_block(torch.arange(2, dtype=torch.int32, device=sim.device))
+    r = x[:, 1] - x[:, 0]
+    want = 0.4 * r / np.linalg.norm(r) ** 3
+    np.testing.assert_allclose(out["acc"].cpu().numpy()[:, 0], want, rtol=1e-14)
+    assert abs(out["pot"].cpu().numpy()[0] + 0.4 / np.linalg.norm(r)) < 1e-15
+    empty = torch.empty(0, dtype=torch.int32, device=sim.device)
+    sim.force_block(empty)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_full_size_sampled(precision):
+    """The headline workload: King W0=7, n = 2^20, 6th order, all particles
+    active in one call (the launch the benchmark times); 256 sampled rows
+    are checked against the oracle."""
+    n = 1 << 20
+    say("full-size force %s n=%d" % (precision, n))
+    model = nbody_ics.king(n, 7.0, 13)
+    d = random_derivs(n, 1313, 8)
+    sim = _sim(model, 6, precision, 1e-8, 0, d)
+    act = torch.arange(n, dtype=torch.int32, device=sim.device)
+    out = sim.force_block(act)
+    torch.cuda.synchronize()
+    sample = nbody_ics.active_subset(n, 256, 1520)
+    ref = oracle_force(6, 1e-8, 0, model.m, model.x, model.v, d[0], None, act=sample)
+    idx = torch.as_tensor(sample.astype(np.int64), device=sim.device)
+    got = {k: t[..., idx] for k, t in out.items()}
+    _check(got, ref, 6, precision, sample.size)

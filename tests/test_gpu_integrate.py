@@ -1,0 +1,317 @@
+"""GPU parity of the O(n) / O(n_act) steps of the hot path (scheduler,
+predictor, corrector + interpolation + time step, initialisation, energy,
+whole block steps) against the CPU oracle on identical inputs.
+
+Integer work (active sets, times, levels) must match exactly; a level may
+differ only where the step criterion lies within rounding of a power of two
+(checked).  FP64 values: relative error <= 1e-12 per particle (rounding order
+differs between the two implementations).
+"""
+import numpy as np
+import pytest
+import torch
+
+import nbody_ics
+import oracle
+from helpers import TICKS, err_stats, rel_err, say
+from oracle import OracleConfig
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(model, order, precision="fp64", eps2=1e-8, n_hard=0, eta=None, k_min=3, k_max=20):
+    from paper_1312_1789_amd import Simulation
+    eta = eta if eta is not None else (0.01 if order == 4 else 0.1)
+    return Simulation(model.m, model.x, model.v, order=order, precision=precision, eps2=eps2, n_hard=n_hard,
+                      eta=eta, eta_start=0.01, k_min=k_min, k_max=k_max)
+
+
+def _ocfg(sim):
+    c = sim.cfg
+    return OracleConfig(order=c.order, eps2=c.eps2, n_hard=c.n_hard, eta=c.eta, eta_start=c.eta_start,
+                        k_min=c.k_min, k_max=c.k_max)
+
+
+def _ostate(h, order):
+    return oracle.State(h["m"], h["x"], h["v"], order, [a.copy() for a in h["d"]], h["t_tick"].copy(),
+                        h["level"].copy())
+
+
+def _random_block_state(n, seed, k_min=3, k_max=20):
+    """Valid block-step times: t_i a multiple of dt_i, all t_i + dt_i >= T."""
+    rng = np.random.default_rng(seed)
+    level = rng.integers(k_min, k_max + 1, n).astype(np.int32)
+    T = 3 * (TICKS >> k_min) + (TICKS >> 5)
+    dt = (1 << (20 - level.astype(np.int64)))
+    # latest multiple of dt not after T, minus 0 or 1 steps is not allowed:
+    t = (T // dt) * dt
+    return t.astype(np.int64), level
+
+
+def test_schedule_exact():
+    for n, seed in [(1, 1), (1000, 2), (5003, 3), (70000, 4)]:
+        model = nbody_ics.plummer(max(n, 2), seed)
+        sim = _sim(model, 4)
+        t, lv = _random_block_state(model.n, seed)
+        sim.load_state(model.x, model.v, [np.zeros((3, model.n))] * 2, t, lv)
+        t_next, act = sim.schedule()
+        nxt = t + (1 << (20 - lv.astype(np.int64)))
+        want_t = int(nxt.min())
+        want = np.nonzero(nxt == want_t)[0]
+        say("schedule n=%d n_act=%d" % (model.n, want.size))
+        assert t_next == want_t
+        np.testing.assert_array_equal(act.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_predict_parity(order, precision):
+    n = 1500
+    model = nbody_ics.plummer(n, 31)
+    sim = _sim(model, order, precision)
+    rng = np.random.default_rng(32)
+    d = [rng.normal(size=(3, n)) * 4.0 ** k for k in range(order - 2)]
+    t, lv = _random_block_state(n, 33)
+    sim.load_state(model.x, model.v, d, t, lv)
+    T = int((t + (1 << (20 - lv.astype(np.int64)))).min())
+    sim.predict(T)
+    got = {k: v.cpu().numpy() for k, v in sim.predicted().items()}
+    os_ = oracle.State(model.m, model.x, model.v, order, d, t, lv)
+    xp, vp, ap, jp = oracle.predict(_ocfg(sim), os_, T)
+    want = {"xp": xp, "vp": vp, "ap": ap, "jp": jp}
+    keys = ["xp", "vp"] + (["ap"] if order >= 6 else []) + (["jp"] if order >= 8 else [])
+    for k in keys:
+        scale = np.sqrt(np.mean(want[k] ** 2))
+        e = np.abs(got[k] - want[k]) / (np.abs(want[k]) + 1e-6 * scale)
+        if precision == "fp64" or k in ("xp", "vp") and precision == "mixed":
+            tol = 1e-14
+        elif precision == "ds" and k in ("xp", "vp"):
+            tol = 2.0 ** -44           # hi + lo keeps ~48 bits
+        else:
+            tol = 2.0 ** -24           # FP32 acceleration / jerk
+        say("predict order %d %s %s max rel %.2e" % (order, precision, k, e.max()))
+        assert e.max() <= tol, (k, e.max())
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_init_parity(order):
+    model = nbody_ics.with_bh_binary(nbody_ics.plummer(1998, 41))
+    sim = _sim(model, order, n_hard=2)
+    sim.init()
+    got = sim.to_numpy()
+    os_ = oracle.State(model.m, model.x, model.v, order)
+    oracle.init(_ocfg(sim), os_)
+    for k in range(order - 2):
+        if order == 8 and k >= 4:
+            assert np.all(got["d"][k] == 0.0)
+            continue
+        st = err_stats(rel_err(got["d"][k], os_.d[k]))
+        say("init order %d d[%d] rms %.2e max %.2e" % (order, k, st["rms"], st["max"]))
+        assert st["rms"] <= 1e-12 and st["max"] <= 1e-9
+    assert np.all(got["t_tick"] == 0)
+    assert np.sum(got["level"] != os_.level) <= 2
+
+
+def _oracle_correct(ocfg, os0, act, T, F):
+    """Oracle corrector, interpolation and level for the active list, composed
+    from the oracle's per-component routines.  Also returns, per active row,
+    the rounding scale of each interpolated derivative (sum of |coefficient x
+    input|; the interpolation cancels heavily for short steps) and the
+    distance of log2(dt_crit) from the nearest integer."""
+    p, q = ocfg.order, ocfg.order // 2
+    newd = [F["acc"], F["jrk"], F["snp"], F["crk"]]
+    x, v = os0.x.copy(), os0.v.copy()
+    d = [a.copy() for a in os0.d]
+    lv = os0.level.copy()
+    scale = np.zeros((p - q, 3, act.size))
+    margin = np.zeros(act.size)
+    dnorm = np.zeros((p, act.size))
+    mats = {}
+    for r, i in enumerate(act):
+        h = (T - os0.t_tick[i]) / TICKS
+        if h not in mats:
+            eye = np.eye(2 * q)
+            mats[h] = np.stack([oracle.hermite_high(p, h, eye[k, :q], eye[k, q:]) for k in range(2 * q)], axis=1)
+        M = mats[h]
+        Dall = np.zeros((p, 3))
+        for c in range(3):
+            D0 = [os0.d[k][c, i] for k in range(q)]
+            D1 = [newd[k][c, r] for k in range(q)]
+            x[c, i], v[c, i] = oracle.hermite_correct(p, h, os0.x[c, i], os0.v[c, i], D0, D1)
+            Dall[:q, c] = D1
+            Dall[q:, c] = oracle.hermite_high(p, h, D0, D1)
+            scale[:, c, r] = np.abs(M) @ np.abs(np.concatenate([D0, D1]))
+        for k in range(p - 2):
+            d[k][:, i] = Dall[k]
+        dnorm[:, r] = np.linalg.norm(Dall, axis=1)
+        dtc = oracle.dt_crit(p, ocfg.eta, dnorm[:, r])
+        lv[i] = oracle.new_level(dtc, int(os0.level[i]), T, ocfg.k_min, ocfg.k_max)
+        margin[r] = abs(np.log2(dtc) - np.round(np.log2(dtc)))
+    return x, v, d, lv, scale, margin, dnorm
+
+
+def _compare_corrected(got, want, act, order, rel_force_err, tag):
+    """x, v to FP64 rounding; interpolated derivatives within their rounding
+    scale (amplified by the force difference); levels equal except where
+    log2(dt_crit) lies within its own rounding uncertainty of an integer
+    (the highest interpolated derivatives cancel heavily for short steps)."""
+    x, v, d, lv, scale, margin, dnorm = want
+    q = order // 2
+    # relative uncertainty of each interpolated |a^(k)| from its rounding
+    # scale, carried into log2(dt_crit): the criterion uses a^(p-3..p-1)
+    # (order 4: a^(2), a^(3)) under a 1/(p-3) power (order 4: a square root)
+    unc = (512 * 2.0 ** -53 + rel_force_err) * np.linalg.norm(scale, axis=1) / np.maximum(dnorm[q:], 1e-300)
+    ks = [2, 3] if order == 4 else list(range(order - 3, order))
+    root = 2.0 if order == 4 else float(order - 3)
+    margin_tol = 4.0 * sum(unc[k - q] for k in ks if k >= q) / root / np.log(2.0) + 1e-12
+    for name, g, w in [("x", got["x"], x), ("v", got["v"], v)]:
+        st = err_stats(rel_err(g[:, act], w[:, act]))
+        say("%s order %d %s rms %.2e max %.2e" % (tag, order, name, st["rms"], st["max"]))
+        assert st["max"] <= 1e-12
+    for k in range(order - 2):
+        diff = np.abs(got["d"][k][:, act] - d[k][:, act])
+        if k < q:
+            bound = 1e-13 * np.abs(d[k][:, act]) + 1e-300 if rel_force_err == 0 else \
+                rel_force_err * np.linalg.norm(d[k][:, act], axis=0)
+        else:
+            bound = (512 * 2.0 ** -53 + rel_force_err) * scale[k - q]
+        ratio = float(np.max(diff / np.maximum(bound, 1e-300)))
+        say("%s order %d d[%d] max |diff| / bound %.2e" % (tag, order, k, ratio))
+        assert ratio <= 1.0, (k, ratio)
+    mism = np.nonzero(got["level"][act] != lv[act])[0]
+    say("%s order %d level mismatches %d of %d (margins %s, allowed %s)"
+        % (tag, order, mism.size, act.size, margin[mism], margin_tol[mism]))
+    assert np.all(margin[mism] < margin_tol[mism])
+    assert np.all(np.abs(got["level"][act].astype(int) - lv[act].astype(int)) <= 1)
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_correct_parity(order):
+    """Identical old state, identical new forces: corrected state,
+    interpolated derivatives and new levels."""
+    n = 2000
+    model = nbody_ics.plummer(n, 51)
+    sim = _sim(model, order)
+    sim.init()
+    h0 = sim.to_numpy()
+    ocfg = _ocfg(sim)
+    os0 = _ostate(h0, order)
+    nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
+    T = int(nxt.min())
+    act = np.nonzero(nxt == T)[0].astype(np.int32)
+    xp, vp, ap, jp = oracle.predict(ocfg, os0, T)
+    F = oracle.force(ocfg, os0.m, xp, vp, ap if order >= 6 else None, jp if order >= 8 else None, act=act)
+    dev = sim.device
+    f = {k: torch.as_tensor(np.ascontiguousarray(F[k]), device=dev) for k in ("acc", "jrk", "snp", "crk")}
+    sim.correct(torch.as_tensor(act, device=dev), T, f)
+    got = sim.to_numpy()
+    assert np.all(got["t_tick"][act] == T)
+    _compare_corrected(got, _oracle_correct(ocfg, os0, act, T, F), act, order, 0.0, "correct")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_step_parity(order, precision):
+    """Whole block steps, each from the GPU's own previous state: identical
+    time and active set (integer work), corrected state within the bound set
+    by the force difference of the precision mode."""
+    model = nbody_ics.with_bh_binary(nbody_ics.plummer(1022, 61))
+    sim = _sim(model, order, precision=precision, n_hard=2)
+    sim.init()
+    ocfg = _ocfg(sim)
+    rel_force = 1e-11 if precision == "fp64" else 3e-5
+    for step in range(10):
+        h0 = sim.to_numpy()
+        os0 = _ostate(h0, order)
+        nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
+        T = int(nxt.min())
+        act = np.nonzero(nxt == T)[0].astype(np.int32)
+        t_g, na_g = sim.step()
+        assert (t_g, na_g) == (T, act.size), step
+        xp, vp, ap, jp = oracle.predict(ocfg, os0, T)
+        F = oracle.force(ocfg, os0.m, xp, vp, ap if order >= 6 else None, jp if order >= 8 else None, act=act)
+        got = sim.to_numpy()
+        assert np.all(got["t_tick"][act] == T)
+        if precision == "fp64":
+            _compare_corrected(got, _oracle_correct(ocfg, os0, act, T, F), act, order, rel_force, "step")
+        else:
+            # MIXED: the corrected state differs by the force error times h
+            want = _oracle_correct(ocfg, os0, act, T, F)
+            st = err_stats(rel_err(got["v"][:, act] - os0.v[:, act], want[1][:, act] - os0.v[:, act]))
+            say("step order %d mixed dv rms %.2e max %.2e" % (order, st["rms"], st["max"]))
+            assert st["rms"] <= 2e-5
+
+
+def test_energy_parity():
+    model = nbody_ics.with_bh_binary(nbody_ics.king(4094, 7.0, 71))
+    sim = _sim(model, 4, n_hard=2)
+    T, W = sim.energy()
+    To, Wo = oracle.energy(_ocfg(sim), model.m, model.x, model.v)
+    say("energy T %.16e / %.16e  W %.16e / %.16e" % (T, To, W, Wo))
+    assert abs(T - To) <= 1e-13 * abs(To)
+    assert abs(W - Wo) <= 1e-12 * abs(Wo)
+
+
+def test_c1_integration_vs_oracle():
+    """The small parity workload: Plummer n=1024, 4th order, eta=0.01,
+    eps=1e-4, FP64, t = 0 -> 0.125: same block-step sequence at the start,
+    energy drift within twice the oracle's, positions close at the end."""
+    model = nbody_ics.plummer(1024, 11)
+    sim = _sim(model, 4, eta=0.01)
+    sim.init()
+    E0 = sum(sim.energy())
+    os_ = _ostate(sim.to_numpy(), 4)
+    ocfg = _ocfg(sim)
+    Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    t_end = TICKS // 8
+    steps = sim.integrate(t_end)
+    st = oracle.integrate(ocfg, os_, t_end)
+    E1 = sum(sim.energy())
+    Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    dg, do = abs((E1 - E0) / E0), abs((Eo1 - Eo0) / Eo0)
+    got = sim.to_numpy()
+    dx = err_stats(np.linalg.norm(got["x"] - os_.x, axis=0))
+    say("C1: steps gpu %d oracle %d; |dE/E| gpu %.3e oracle %.3e; |dx| rms %.2e max %.2e; level diffs %d"
+        % (steps, st["steps"], dg, do, dx["rms"], dx["max"], int(np.sum(got["level"] != os_.level))))
+    assert np.all(got["t_tick"] == t_end)
+    assert dg <= 2.0 * do + 1e-12
+    assert abs(steps - st["steps"]) <= 0.02 * st["steps"]
+    assert dx["rms"] < 1e-8
+
+
+def test_mixed_energy_drift_matches_fp64():
+    """6th order, Plummer n=4096, eta=0.1, to t = 1/4: the MIXED force keeps
+    |dE/E| within twice the oracle's drift."""
+    model = nbody_ics.plummer(4096, 12)
+    drift = {}
+    for prec in ("mixed", "fp64"):
+        sim = _sim(model, 6, precision=prec, eta=0.1)
+        sim.init()
+        E0 = sum(sim.energy())
+        sim.integrate(TICKS // 4)
+        E1 = sum(sim.energy())
+        drift[prec] = abs((E1 - E0) / E0)
+    ocfg = OracleConfig(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
+    os_ = oracle.State(model.m, model.x, model.v, 6)
+    oracle.init(ocfg, os_)
+    Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    oracle.integrate(ocfg, os_, TICKS // 4)
+    Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    do = abs((Eo1 - Eo0) / Eo0)
+    say("drift mixed %.3e fp64 %.3e oracle %.3e" % (drift["mixed"], drift["fp64"], do))
+    assert drift["fp64"] <= 2.0 * do + 1e-13
+    assert drift["mixed"] <= 2.0 * do + 1e-10
+
+
+def test_nonfinite_is_reported():
+    from paper_1312_1789_amd import abi
+    model = nbody_ics.plummer(512, 81)
+    sim = _sim(model, 4)
+    sim.init()
+    h = sim.to_numpy()
+    h["x"][0, 5] = np.nan
+    sim.load_state(h["x"], h["v"], h["d"], h["t_tick"], h["level"])
+    with pytest.raises(abi.NBodyError) as e:
+        for _ in range(200):
+            sim.step()
+    assert e.value.status == abi.NBODY_E_NONFINITE
