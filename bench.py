@@ -162,6 +162,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB on the device (a kernel of known traffic that "
+                         "scales the HBM byte counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -175,6 +178,13 @@ def main():
         sys.exit(1)
     from paper_1312_1789_amd import abi
     abi.lib()
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calibrate_copy_mib, args.calibrate_copy_mib))
+        del src, dst
 
     t0 = time.perf_counter()
     model = nbody_ics.king(args.n, 7.0, 13)

@@ -51,9 +51,10 @@ typedef enum {
  * energy are FP64 in every mode). */
 typedef enum {
     NBODY_FP64 = 0,  /* all FP64 */
-    NBODY_MIXED = 1, /* FP64 position / velocity differences, FP32 rsqrt and
-                        pairwise arithmetic, FP32 partial sums over j-chunks of
-                        at most 64 terms added into FP64 accumulators */
+    NBODY_MIXED = 1, /* double-single (hi + lo float) position and velocity
+                        differences, FP32 rsqrt and pairwise arithmetic, FP32
+                        partial sums over j-chunks of 128 terms added into FP64
+                        accumulators */
     NBODY_DS = 2     /* FP32-only hardware: double-single (hi + lo float)
                         positions and velocities, FP32 arithmetic, compensated
                         (two-sum) double-single accumulation of every term */
@@ -170,9 +171,12 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
 
 /* Launch shape of the force kernel: ni = active particles per lane (1 or 2),
  * block = threads per workgroup (64, 128 or 256), n_split = j-range splits
- * (0 = chosen per call from n_act).  Results do not depend on ni or block;
- * they depend on n_split only through the FP64 summation order. */
-nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split);
+ * (0 = chosen per call from n_act), jpath = how j records reach the lanes
+ * (0 = default for the precision, 1 = wave-uniform scalar loads, 2 = LDS
+ * tiles).  Results do not depend on ni, block or jpath; they depend on n_split
+ * only through the FP64 summation order (and, in MIXED mode, where the FP32
+ * chunks start). */
+nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split, int32_t jpath);
 
 /* Phase timers of nbody_step, measured with HIP events on the context's
  * stream.  nbody_set_timing(ctx, 1) creates the events and starts

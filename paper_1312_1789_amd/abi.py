@@ -83,7 +83,7 @@ def lib():
             "nbody_energy": [P, C.POINTER(nbody_state), C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "nbody_get_predicted": [P, P, P, P, P],
             "nbody_get_stats": [P, C.POINTER(nbody_stats)],
-            "nbody_set_launch": [P, C.c_int32, C.c_int32, C.c_int32],
+            "nbody_set_launch": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "nbody_set_timing": [P, C.c_int32],
             "nbody_get_timers": [P, C.POINTER(C.c_double), C.POINTER(I64)],
         }
@@ -181,8 +181,8 @@ def nbody_get_stats(ctx: int) -> nbody_stats:
     return s
 
 
-def nbody_set_launch(ctx: int, ni: int, block: int, n_split: int) -> None:
-    _check(lib().nbody_set_launch(C.c_void_p(ctx), int(ni), int(block), int(n_split)), "nbody_set_launch")
+def nbody_set_launch(ctx: int, ni: int, block: int, n_split: int, jpath: int = 0) -> None:
+    _check(lib().nbody_set_launch(C.c_void_p(ctx), int(ni), int(block), int(n_split), int(jpath)), "nbody_set_launch")
 
 
 def nbody_set_timing(ctx: int, enable: bool) -> None:

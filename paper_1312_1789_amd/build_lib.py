@@ -23,7 +23,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    "-Wall", "-Wno-unused-function",
+    "-fno-strict-aliasing", "-Wall", "-Wno-unused-function",
 ]
 
 

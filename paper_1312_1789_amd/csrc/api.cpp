@@ -88,6 +88,7 @@ nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec
     a.ni = ctx->ni;
     a.block = ctx->block;
     a.n_split = ctx->n_split;
+    a.jpath = ctx->jpath;
     int used = 0;
     NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
     ctx->stats.interactions += double(n_act) * double(ctx->cfg.n);
@@ -203,15 +204,17 @@ nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5], int64_t *steps)
     return NBODY_OK;
 }
 
-nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split)
+nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split, int32_t jpath)
 {
     if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (jpath < 0 || jpath > 2) return fail(NBODY_E_INVALID, "jpath must be 0 (auto), 1 (scalar) or 2 (LDS)");
     if (ni != 1 && ni != 2) return fail(NBODY_E_INVALID, "ni must be 1 or 2");
     if (block != 64 && block != 128 && block != 256) return fail(NBODY_E_INVALID, "block must be 64, 128 or 256");
     if (n_split < 0 || n_split > 65535) return fail(NBODY_E_INVALID, "n_split must be in [0, 65535]");
     ctx->ni = ni;
     ctx->block = block;
     ctx->n_split = n_split;
+    ctx->jpath = jpath;
     return NBODY_OK;
 }
 

@@ -60,14 +60,6 @@ k_predict(int64_t n, const double *__restrict__ m, const double *__restrict__ x,
         if constexpr (P >= 6) { r.ax = ap[0]; r.ay = ap[1]; r.az = ap[2]; }
         if constexpr (P >= 8) { r.jx = jp[0]; r.jy = jp[1]; r.jz = jp[2]; }
         static_cast<RecF64<P> *>(rec_out)[i] = r;
-    } else if constexpr (PREC == NBODY_MIXED) {
-        RecMx<P> r{};
-        r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
-        r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
-        r.m = float(mi);
-        if constexpr (P >= 6) { r.ax = float(ap[0]); r.ay = float(ap[1]); r.az = float(ap[2]); }
-        if constexpr (P >= 8) { r.jx = float(jp[0]); r.jy = float(jp[1]); r.jz = float(jp[2]); }
-        static_cast<RecMx<P> *>(rec_out)[i] = r;
     } else {
         RecDS<P> r{};
         float hx[3], lx[3], hv[3], lv[3];
@@ -99,11 +91,6 @@ k_unpack(int64_t n, const void *__restrict__ rec, double *__restrict__ xp, doubl
     double X[3], V[3], A[3] = {0, 0, 0}, J[3] = {0, 0, 0};
     if constexpr (PREC == NBODY_FP64) {
         const RecF64<P> r = static_cast<const RecF64<P> *>(rec)[i];
-        X[0] = r.x; X[1] = r.y; X[2] = r.z; V[0] = r.vx; V[1] = r.vy; V[2] = r.vz;
-        if constexpr (P >= 6) { A[0] = r.ax; A[1] = r.ay; A[2] = r.az; }
-        if constexpr (P >= 8) { J[0] = r.jx; J[1] = r.jy; J[2] = r.jz; }
-    } else if constexpr (PREC == NBODY_MIXED) {
-        const RecMx<P> r = static_cast<const RecMx<P> *>(rec)[i];
         X[0] = r.x; X[1] = r.y; X[2] = r.z; V[0] = r.vx; V[1] = r.vy; V[2] = r.vz;
         if constexpr (P >= 6) { A[0] = r.ax; A[1] = r.ay; A[2] = r.az; }
         if constexpr (P >= 8) { J[0] = r.jx; J[1] = r.jy; J[2] = r.jz; }

@@ -15,7 +15,7 @@ constexpr int64_t kTicksPerUnit = int64_t(1) << kLevelMax;
 constexpr int kSchedBlock = 256;            // threads per scheduler block
 constexpr int kSchedPerThread = 4;          // particles per scheduler thread
 constexpr int kSchedChunk = kSchedBlock * kSchedPerThread;
-constexpr int kMixedChunk = 64;             // FP32 partial-sum length in MIXED mode
+constexpr int kMixedChunk = 128;            // FP32 partial-sum length in MIXED mode
 constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act_pad * n_split)
 constexpr int kMaxComp = 13;                // acc3 + jerk3 + snap3 + crackle3 + pot
 
@@ -60,6 +60,7 @@ struct ForceArgs {
     double *out[5];         // acc, jrk, snp, crk, pot ([3][n_act] / [n_act]); may be null
     double *part;           // partial-sum scratch
     int ni, block, n_split; // launch shape (n_split 0 = auto)
+    int jpath;              // 0 auto, 1 scalar loads, 2 LDS tiles
 };
 
 hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split);
@@ -101,7 +102,7 @@ struct nbody_ctx {
     nb::Layout lay;
     int device;
     bool predicted;
-    int ni, block, n_split;
+    int ni, block, n_split, jpath;
     nbody_stats stats;
     bool timing;              // record phase events in nbody_step
     hipEvent_t ev[6];         // phase boundaries (created on first enable)

@@ -17,15 +17,8 @@ template <> struct alignas(16) RecF64<4> { double x, y, z, m, vx, vy, vz, pad; }
 template <> struct alignas(16) RecF64<6> { double x, y, z, m, vx, vy, vz, ax, ay, az; };                // 80 B
 template <> struct alignas(16) RecF64<8> { double x, y, z, m, vx, vy, vz, ax, ay, az, jx, jy, jz, pad; }; // 112 B
 
-// MIXED mode: FP64 positions and velocities (their differences are taken in
-// FP64), FP32 mass, acceleration and jerk.
-template <int P> struct RecMx;
-template <> struct alignas(16) RecMx<4> { double x, y, z, vx, vy, vz; float m, p0, p1, p2; };                   // 64 B
-template <> struct alignas(16) RecMx<6> { double x, y, z, vx, vy, vz; float m, ax, ay, az; };                   // 64 B
-template <> struct alignas(16) RecMx<8> { double x, y, z, vx, vy, vz; float m, ax, ay, az, jx, jy, jz, p0; };   // 80 B
-
-// DS mode: double-single positions and velocities (hi = float(x),
-// lo = float(x - hi)), FP32 mass, acceleration and jerk.
+// MIXED and DS modes: double-single positions and velocities
+// (hi = float(x), lo = float(x - hi)), FP32 mass, acceleration and jerk.
 template <int P> struct RecDS;
 template <> struct alignas(16) RecDS<4> {
     float xh, yh, zh, m, xl, yl, zl, vxh, vyh, vzh, vxl, vyl, vzl, p0, p1, p2;                             // 64 B
@@ -38,7 +31,6 @@ template <> struct alignas(16) RecDS<8> {
 };
 
 static_assert(sizeof(RecF64<4>) == 64 && sizeof(RecF64<6>) == 80 && sizeof(RecF64<8>) == 112, "f64 rec");
-static_assert(sizeof(RecMx<4>) == 64 && sizeof(RecMx<6>) == 64 && sizeof(RecMx<8>) == 80, "mixed rec");
 static_assert(sizeof(RecDS<4>) == 64 && sizeof(RecDS<6>) == 64 && sizeof(RecDS<8>) == 80, "ds rec");
 
 // Reciprocal square root in FP64: the hardware estimate (about 24 correct

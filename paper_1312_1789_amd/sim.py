@@ -68,8 +68,8 @@ class Simulation:
             pass
 
     # ---- entry points -------------------------------------------------------
-    def set_launch(self, ni: int = 1, block: int = 256, n_split: int = 0):
-        abi.nbody_set_launch(self.ctx, ni, block, n_split)
+    def set_launch(self, ni: int = 1, block: int = 256, n_split: int = 0, jpath: int = 0):
+        abi.nbody_set_launch(self.ctx, ni, block, n_split, jpath)
 
     def set_timing(self, enable: bool = True):
         abi.nbody_set_timing(self.ctx, enable)

@@ -69,5 +69,5 @@ def test_null_context_is_rejected():
     L = abi.lib()
     assert L.nbody_destroy(None) == abi.NBODY_E_INVALID
     assert L.nbody_step(None, None, None, None) == abi.NBODY_E_INVALID
-    assert L.nbody_set_launch(None, 1, 256, 0) == abi.NBODY_E_INVALID
+    assert L.nbody_set_launch(None, 1, 256, 0, 0) == abi.NBODY_E_INVALID
     assert L.nbody_get_predicted(None, None, None, None, None) == abi.NBODY_E_INVALID

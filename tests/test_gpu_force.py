@@ -91,15 +91,16 @@ def test_unsorted_active_list_permutes_rows(small_case):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_launch_shapes_and_determinism(small_case, precision):
-    """ni and block do not change any bit; reruns are bitwise identical; the
-    split count changes only the summation order (in MIXED mode also where the
-    FP32 chunk sums start, so up to FP32 rounding)."""
+    """ni, block and the j path (scalar loads or LDS tiles) do not change any
+    bit; reruns are bitwise identical; the split count changes only the
+    summation order (in MIXED mode also where the FP32 chunk sums start, so up
+    to FP32 rounding)."""
     model, eps2, n_hard, d = small_case
     sim = _sim(model, 6, precision, eps2, n_hard, d)
     act = torch.as_tensor(nbody_ics.active_subset(model.n, 700, 1530), device=sim.device)
     ref = None
-    for ni, block in [(1, 256), (2, 256), (1, 64), (2, 128)]:
-        sim.set_launch(ni, block, 5)
+    for ni, block, jpath in [(1, 256, 1), (2, 256, 1), (1, 64, 2), (2, 128, 2), (1, 256, 2), (2, 256, 2)]:
+        sim.set_launch(ni, block, 5, jpath)
         out = {k: t.cpu().numpy().copy() for k, t in sim.force_block(act).items()}
         if ref is None:
             ref = out
