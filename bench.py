@@ -40,7 +40,7 @@ FLOPS_LITERATURE = {4: 60, 6: 97, 8: 144}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "force_mixed_p6_n1M_traffic.md")
-FORCE_SOURCES = [os.path.join(ROOT, "paper_1312_1789_amd", "csrc", f) for f in ("force.hip", "records.h")]
+FORCE_SOURCES = [os.path.join(ROOT, "paper_1312_1789_amd", "csrc", f) for f in ("force.hip", "pairwise.h", "records.h")]
 
 
 def log(*a):
