@@ -187,6 +187,71 @@ nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t
 nbody_status nbody_set_timing(nbody_ctx *ctx, int32_t enable);
 nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5] /* host */, int64_t *steps /* host */);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent clusters (separate N-body systems that share
+ * one configuration) advanced together.  Particles of cluster c are
+ * [off[c], off[c+1]) of one concatenated state (all arrays [3][n] with
+ * n = off[n_clusters]); pairs never cross clusters; n_hard counts from the
+ * first particle of each cluster.  Each batched step advances every cluster
+ * by one block step of its own (its own t_next and active set), with the
+ * same arithmetic as nbody_step.  The launch sequence of a step does not
+ * depend on the data (fixed grids; a persistent force kernel takes
+ * (cluster, i-tile, j-split) work items from a device queue, largest
+ * clusters first), so it can be captured once in a HIP graph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct nbody_batch nbody_batch;
+
+/* Workspace bytes for a batch.  cfg->n = off[n_clusters]; off: HOST array of
+ * n_clusters + 1 offsets, off[0] = 0, every cluster at least 2 particles,
+ * 1 <= n_clusters <= 65535, cfg->n_hard <= the smallest cluster. */
+nbody_status nbody_batch_workspace_size(const nbody_config *cfg, int32_t n_clusters, const int64_t *off /* host */,
+                                        size_t *bytes /* host */);
+
+/* Create a batch context (same workspace and stream rules as nbody_create;
+ * graph capture needs a stream other than the default stream). */
+nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, const int64_t *off /* host */,
+                                void *workspace, size_t bytes, void *stream, nbody_batch **out);
+nbody_status nbody_batch_destroy(nbody_batch *b);
+
+/* nbody_init for every cluster (each at t = 0, forces from its own particles). */
+nbody_status nbody_batch_init(nbody_batch *b, nbody_state *state);
+
+/* Clusters whose next block time would exceed t_end_tick rest (take no step);
+ * default: no limit. */
+nbody_status nbody_batch_set_end(nbody_batch *b, int64_t t_end_tick);
+
+/* Enqueue k batched steps directly (asynchronous; no host round trip). */
+nbody_status nbody_batch_step(nbody_batch *b, nbody_state *state, int64_t k);
+
+/* Capture one batched step on `state` (its pointers are baked in) into a HIP
+ * graph; nbody_batch_replay launches it k times.  A new capture replaces the
+ * old one. */
+nbody_status nbody_batch_capture(nbody_batch *b, nbody_state *state);
+nbody_status nbody_batch_replay(nbody_batch *b, int64_t k);
+
+/* Synchronising poll: *n_live (host) = clusters that took a step in the last
+ * batched step (0 once every cluster rests); t_cur (host, n_clusters
+ * entries, may be NULL) = each cluster's time (its last completed step). */
+nbody_status nbody_batch_poll(nbody_batch *b, int64_t *n_live, int64_t *t_cur);
+
+/* The last batched step's work (synchronising): aoff (HOST, n_clusters + 1) =
+ * offsets of the clusters' active lists in the concatenated list; act (DEVICE,
+ * room for n, may be NULL) = the list, increasing within each cluster;
+ * forces (DEVICE, may be NULL) = [order/2][3][n_act] FP64 force derivatives
+ * (acc, jerk, snap, crackle) at the step's end, row q for act[q]. */
+nbody_status nbody_batch_last_step(nbody_batch *b, int64_t *aoff, int32_t *act, double *forces);
+
+/* Per-cluster FP64 energies (HOST arrays of n_clusters), as nbody_energy. */
+nbody_status nbody_batch_energy(nbody_batch *b, const nbody_state *state, double *ekin, double *epot);
+
+/* Counters over all clusters since creation (steps = batched steps). */
+nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out);
+
+/* Persistent force launch: force_grid workgroups (0 = as many as fit on the
+ * device at once) and target_items work items aimed for per cluster when its
+ * active set is small (1..64, 0 = 16; the j-range is split to reach it). */
+nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *nbody_last_error(void);
 

@@ -32,6 +32,9 @@ EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
     "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
+    "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
+    "nbody_batch_set_end", "nbody_batch_step", "nbody_batch_capture", "nbody_batch_replay", "nbody_batch_poll",
+    "nbody_batch_last_step", "nbody_batch_energy", "nbody_batch_get_stats", "nbody_batch_set_launch",
     "nbody_last_error",
 )
 
@@ -86,6 +89,20 @@ def lib():
             "nbody_set_launch": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "nbody_set_timing": [P, C.c_int32],
             "nbody_get_timers": [P, C.POINTER(C.c_double), C.POINTER(I64)],
+            "nbody_batch_workspace_size": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), C.POINTER(C.c_size_t)],
+            "nbody_batch_create": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), P, C.c_size_t, P,
+                                   C.POINTER(P)],
+            "nbody_batch_destroy": [P],
+            "nbody_batch_init": [P, C.POINTER(nbody_state)],
+            "nbody_batch_set_end": [P, I64],
+            "nbody_batch_step": [P, C.POINTER(nbody_state), I64],
+            "nbody_batch_capture": [P, C.POINTER(nbody_state)],
+            "nbody_batch_replay": [P, I64],
+            "nbody_batch_poll": [P, C.POINTER(I64), C.POINTER(I64)],
+            "nbody_batch_last_step": [P, C.POINTER(I64), P, P],
+            "nbody_batch_energy": [P, C.POINTER(nbody_state), C.POINTER(C.c_double), C.POINTER(C.c_double)],
+            "nbody_batch_get_stats": [P, C.POINTER(nbody_stats)],
+            "nbody_batch_set_launch": [P, C.c_int32, C.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -198,3 +215,82 @@ def nbody_get_timers(ctx: int):
     steps = C.c_int64(0)
     _check(lib().nbody_get_timers(C.c_void_p(ctx), ms, C.byref(steps)), "nbody_get_timers")
     return dict(zip(PHASES, list(ms))), int(steps.value)
+
+
+# ---- batched form ------------------------------------------------------------
+def _offsets(off):
+    off = [int(o) for o in off]
+    return len(off) - 1, (C.c_int64 * len(off))(*off)
+
+
+def nbody_batch_workspace_size(cfg: nbody_config, off) -> int:
+    nc, arr = _offsets(off)
+    b = C.c_size_t(0)
+    _check(lib().nbody_batch_workspace_size(C.byref(cfg), nc, arr, C.byref(b)), "nbody_batch_workspace_size")
+    return int(b.value)
+
+
+def nbody_batch_create(cfg: nbody_config, off, workspace: int, nbytes: int, stream: int = 0) -> int:
+    nc, arr = _offsets(off)
+    out = C.c_void_p(0)
+    _check(lib().nbody_batch_create(C.byref(cfg), nc, arr, C.c_void_p(workspace), nbytes, C.c_void_p(stream),
+                                    C.byref(out)), "nbody_batch_create")
+    return int(out.value)
+
+
+def nbody_batch_destroy(b: int) -> None:
+    _check(lib().nbody_batch_destroy(C.c_void_p(b)), "nbody_batch_destroy")
+
+
+def nbody_batch_init(b: int, st: nbody_state) -> None:
+    _check(lib().nbody_batch_init(C.c_void_p(b), C.byref(st)), "nbody_batch_init")
+
+
+def nbody_batch_set_end(b: int, t_end_tick: int) -> None:
+    _check(lib().nbody_batch_set_end(C.c_void_p(b), int(t_end_tick)), "nbody_batch_set_end")
+
+
+def nbody_batch_step(b: int, st: nbody_state, k: int = 1) -> None:
+    _check(lib().nbody_batch_step(C.c_void_p(b), C.byref(st), int(k)), "nbody_batch_step")
+
+
+def nbody_batch_capture(b: int, st: nbody_state) -> None:
+    _check(lib().nbody_batch_capture(C.c_void_p(b), C.byref(st)), "nbody_batch_capture")
+
+
+def nbody_batch_replay(b: int, k: int = 1) -> None:
+    _check(lib().nbody_batch_replay(C.c_void_p(b), int(k)), "nbody_batch_replay")
+
+
+def nbody_batch_poll(b: int, n_clusters: int):
+    """(clusters that stepped in the last batched step, list of cluster times)."""
+    live = C.c_int64(0)
+    t = (C.c_int64 * n_clusters)()
+    _check(lib().nbody_batch_poll(C.c_void_p(b), C.byref(live), t), "nbody_batch_poll")
+    return int(live.value), list(t)
+
+
+def nbody_batch_last_step(b: int, n_clusters: int, act: int = 0, forces: int = 0):
+    """Offsets (n_clusters + 1) of the last step's active lists; fills the
+    device buffers act / forces when given."""
+    aoff = (C.c_int64 * (n_clusters + 1))()
+    _check(lib().nbody_batch_last_step(C.c_void_p(b), aoff, C.c_void_p(act or None), C.c_void_p(forces or None)),
+           "nbody_batch_last_step")
+    return list(aoff)
+
+
+def nbody_batch_energy(b: int, st: nbody_state, n_clusters: int):
+    T = (C.c_double * n_clusters)()
+    W = (C.c_double * n_clusters)()
+    _check(lib().nbody_batch_energy(C.c_void_p(b), C.byref(st), T, W), "nbody_batch_energy")
+    return list(T), list(W)
+
+
+def nbody_batch_get_stats(b: int) -> nbody_stats:
+    s = nbody_stats()
+    _check(lib().nbody_batch_get_stats(C.c_void_p(b), C.byref(s)), "nbody_batch_get_stats")
+    return s
+
+
+def nbody_batch_set_launch(b: int, force_grid: int = 0, target_items: int = 0) -> None:
+    _check(lib().nbody_batch_set_launch(C.c_void_p(b), int(force_grid), int(target_items)), "nbody_batch_set_launch")

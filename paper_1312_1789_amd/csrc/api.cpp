@@ -13,22 +13,7 @@
 
 namespace {
 
-thread_local char g_err[512] = "";
-
-nbody_status fail(nbody_status s, const char *fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
-    va_end(ap);
-    return s;
-}
-
-#define NB_HIP(call)                                                                                 \
-    do {                                                                                             \
-        hipError_t e_ = (call);                                                                      \
-        if (e_ != hipSuccess) return fail(NBODY_E_HIP, "%s: %s", #call, hipGetErrorString(e_));      \
-    } while (0)
+using nb::fail;
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
@@ -106,6 +91,23 @@ nbody_status read_scalars(nbody_ctx *ctx, nb::DevScalars *h)
 
 namespace nb {
 
+nbody_status check_config_checked(const nbody_config *c) { return ::check_config(c); }
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+nbody_status fail(nbody_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+const char *last_error() { return g_err; }
+
 Layout make_layout(const nbody_config &c)
 {
     Layout L{};
@@ -134,7 +136,7 @@ Layout make_layout(const nbody_config &c)
 
 extern "C" {
 
-const char *nbody_last_error(void) { return g_err; }
+const char *nbody_last_error(void) { return nb::last_error(); }
 
 nbody_status nbody_workspace_size(const nbody_config *cfg, size_t *bytes)
 {
@@ -369,7 +371,7 @@ nbody_status nbody_energy(nbody_ctx *ctx, const nbody_state *st, double *ekin, d
     if (!ekin || !epot) return fail(NBODY_E_INVALID, "ekin and epot are required");
     int np = 0;
     double *part = ws_at<double>(ctx, ctx->lay.energy);
-    NB_HIP(nb::launch_energy(ctx->cfg.n, hard_count(ctx->cfg), ctx->cfg.eps2, st->m, st->x, st->v, part, &np,
+    NB_HIP(nb::launch_energy(ctx->cfg.n, ctx->cfg.n, hard_count(ctx->cfg), ctx->cfg.eps2, st->m, st->x, st->v, part, &np,
                              ctx->stream));
     std::vector<double> h(2 * size_t(np));
     NB_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));

@@ -1,0 +1,76 @@
+// batch.h -- device-side plan and launch arguments of the batched form (many
+// independent clusters in one step sequence).  Not part of the public C-ABI.
+#pragma once
+
+#include "internal.h"
+
+namespace nb {
+
+constexpr int kBatchMaxTarget = 64;   // largest items-per-cluster target the plan accepts
+constexpr int kBatchITile = 256;      // active rows per work item (= force workgroup size)
+constexpr int kBatchSchedBlock = 1024;  // particles per scheduling block
+
+// Written by the plan kernel of every batched step and read by the kernels
+// after it.  Arrays sized n_clusters + 1 (the last entry of a scanned array
+// holds its total).
+struct BatchPlan {
+    unsigned long long queue;   // next work item of the persistent force kernel
+    int64_t t_end;              // clusters whose next time exceeds this do not step
+    int64_t n_live;             // clusters that stepped in the last plan
+    int64_t pad[5];
+    int64_t *nact;              // [nc]   active particles per cluster
+    int64_t *aoff;              // [nc+1] offsets of the clusters' active lists
+    int64_t *ioff;              // [nc+1] first work item of each cluster rank
+    int64_t *poff;              // [nc+1] offsets of the clusters' split partials (doubles)
+    int64_t *jchunk;            // [nc]   j-range per split
+    int32_t *split;             // [nc]   j-splits per cluster
+    int64_t *tcur;              // [nc]   time of the cluster's last completed step
+};
+
+struct BatchCounters {
+    int64_t steps;
+    int64_t sum_n_act;
+    int64_t interactions;
+    unsigned long long underflow;
+    unsigned long long nonfinite;
+    int64_t pad[3];
+};
+
+// Everything a batched launch needs; all pointers are device addresses inside
+// the batch workspace except the state, which the caller passes per call.
+struct BatchLaunch {
+    int nc;                     // clusters
+    int nb;                     // scheduling blocks per cluster (largest cluster / 1024, rounded up)
+    int64_t n;                  // particles in all clusters
+    const int64_t *off;         // [nc+1] cluster offsets
+    const int32_t *ord;         // [nc]   clusters by decreasing size
+    int32_t *cid;               // [n]    cluster of each particle
+    int64_t *tnext;             // [nc]   next block time of each cluster
+    int64_t *bmin;              // [nc][nb]
+    int32_t *bcnt;              // [nc][nb]
+    int64_t *boff;              // [nc][nb]
+    BatchPlan *plan;
+    BatchCounters *ctr;
+    int32_t *act;               // [n] concatenated active lists
+    double *part;               // split partials
+    double *force;              // [12][n] step forces by active row
+    double eps2;
+    int64_t n_hard;             // per cluster; every pair is unsoftened when eps2 == 0
+    int force_grid;             // workgroups of the persistent force kernel
+    int target_items;           // work items aimed for per cluster
+};
+
+hipError_t batch_cid(const BatchLaunch &L, hipStream_t s);
+hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_active, int order, hipStream_t s);
+hipError_t batch_predict(const BatchLaunch &L, const nbody_state &st, int order, int precision, void *rec,
+                         hipStream_t s);
+// Reset the work queue (a second force pass on the same plan).
+hipError_t batch_requeue(const BatchLaunch &L, hipStream_t s);
+hipError_t batch_force(const BatchLaunch &L, int order, int precision, const void *rec, hipStream_t s);
+hipError_t batch_reduce(const BatchLaunch &L, int order, double *o0, double *o1, double *o2, double *o3,
+                        hipStream_t s);
+hipError_t batch_correct(const BatchLaunch &L, const nbody_config &c, const nbody_state &st, hipStream_t s);
+// Workgroups of the persistent force kernel that fit on the device at once.
+int batch_force_resident(int order, int precision, int device);
+
+}  // namespace nb

@@ -1,0 +1,500 @@
+// batch.hip -- many independent clusters advanced together: every call of a
+// batched step gives each cluster one block step of its own (its own t_next
+// and active set), with a fixed sequence of launches whose grids do not
+// depend on the data, so one step can be captured in a HIP graph and
+// replayed without the host.
+//
+// Sequence of one batched step:
+//   k_b_min / k_b_count  per (cluster, 1024-particle block): next-time minima,
+//                        the cluster's t_next, active counts;
+//   k_b_plan             one block: active offsets, j-splits and work items
+//                        per cluster (largest clusters first), counters, and
+//                        the reset of the work queue;
+//   k_b_compact          ordered active lists;
+//   k_b_predict          every particle to its cluster's t_next;
+//   k_b_force            persistent: workgroups pull (cluster, i-tile, j-split)
+//                        items from a device queue until it is empty;
+//   k_b_reduce           split partials summed in split order;
+//   k_b_correct          corrector, interpolation and new steps.
+// Method as in the single-system kernels (paper: Abstract; Sec. "Codes
+// description"): Hermite block steps of order 4, 6 or 8 and direct-summation
+// softened gravity with its derivatives (Nitadori & Makino 2008).
+#include <climits>
+
+#include "batch.h"
+#include "hermite.h"
+#include "pairwise.h"
+
+namespace nb {
+namespace {
+
+constexpr int kBBlock = kBatchSchedBlock;
+constexpr int kBThreads = 256;  // threads per scheduling block (4 particles each)
+constexpr int kFBlock = kBatchITile;
+constexpr int kFTile = 128;     // j records per LDS tile
+
+__device__ __forceinline__ int64_t b_next(const int64_t *t_tick, const int32_t *level, int64_t i)
+{
+    return t_tick[i] + (int64_t(1) << (kLevelMax - level[i]));
+}
+
+// Block b of cluster c covers [off[c] + b*kBBlock, min(off[c] + (b+1)*kBBlock, off[c+1])).
+__global__ void __launch_bounds__(kBThreads)
+k_b_min(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+        int nb, int64_t *__restrict__ bmin)
+{
+    __shared__ int64_t sm[kBThreads];
+    const int c = blockIdx.y, b = blockIdx.x;
+    const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
+    int64_t mn = INT64_MAX;
+    for (int k = 0; k < kBBlock / kBThreads; ++k) {
+        const int64_t i = lo + int64_t(k) * kBThreads + threadIdx.x;
+        if (i < hi && i < lo + kBBlock) {
+            const int64_t t = b_next(t_tick, level, i);
+            mn = t < mn ? t : mn;
+        }
+    }
+    sm[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kBThreads / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s && sm[threadIdx.x + s] < sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmin[int64_t(c) * nb + b] = sm[0];
+}
+
+// Cluster minimum (from the block minima), then this block's active count.
+// all_active != 0 marks every particle active (initialisation).
+__global__ void __launch_bounds__(kBThreads)
+k_b_count(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+          int nb, const int64_t *__restrict__ bmin, int all_active, const BatchPlan *__restrict__ pl,
+          int64_t *__restrict__ tnext, int32_t *__restrict__ bcnt)
+{
+    __shared__ int64_t sm[kBThreads];
+    __shared__ int cnt[kBThreads];
+    const int c = blockIdx.y, b = blockIdx.x;
+    int64_t mn = INT64_MAX;
+    for (int k = threadIdx.x; k < nb; k += kBThreads) {
+        const int64_t v = bmin[int64_t(c) * nb + k];
+        mn = v < mn ? v : mn;
+    }
+    sm[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kBThreads / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s && sm[threadIdx.x + s] < sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    // initialisation: every particle at t = 0; otherwise clusters past t_end rest
+    const int64_t tn = all_active ? 0 : sm[0];
+    const bool live = all_active || tn <= pl->t_end;
+    const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
+    int k0 = 0;
+    for (int k = 0; k < kBBlock / kBThreads; ++k) {
+        const int64_t i = lo + int64_t(k) * kBThreads + threadIdx.x;
+        if (live && i < hi && i < lo + kBBlock && (all_active || b_next(t_tick, level, i) == tn)) ++k0;
+    }
+    cnt[threadIdx.x] = k0;
+    __syncthreads();
+    for (int s = kBThreads / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bcnt[int64_t(c) * nb + b] = cnt[0];
+        if (b == 0) tnext[c] = tn;
+    }
+}
+
+// Exclusive scan of v[0..n) in one block (chunks of kBThreads, running carry).
+__device__ void block_scan(int64_t *v, int n, int64_t *sh)
+{
+    int64_t carry = 0;
+    for (int c0 = 0; c0 < n; c0 += kBThreads) {
+        const int c = c0 + threadIdx.x;
+        const int64_t x = c < n ? v[c] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int o = 1; o < kBThreads; o <<= 1) {
+            const int64_t add = int(threadIdx.x) >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (c < n) v[c] = carry + sh[threadIdx.x] - x;
+        carry += sh[kBThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) v[n] = carry;
+    __syncthreads();
+}
+
+// The plan of one batched step (one block).  For every cluster: active count
+// and offset, j-splits and work items; items are numbered in the cluster
+// order ord[] (largest clusters first) so the persistent force kernel starts
+// with the longest items.  Also resets the work queue and adds the step's
+// interactions to the counters.
+__global__ void __launch_bounds__(kBThreads)
+k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
+         const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int64_t *__restrict__ boff, BatchPlan *__restrict__ pl, int ncomp,
+         int target_items, BatchCounters *__restrict__ ctr)
+{
+    __shared__ int64_t sh[kBThreads];
+    // per-cluster active counts and block offsets inside the cluster
+    for (int c = threadIdx.x; c < nc; c += kBThreads) {
+        int64_t s = 0;
+        for (int b = 0; b < nb; ++b) {
+            boff[int64_t(c) * nb + b] = s;
+            s += bcnt[int64_t(c) * nb + b];
+        }
+        pl->nact[c] = s;
+        pl->aoff[c] = s;
+        if (s > 0) pl->tcur[c] = tnext[c];
+    }
+    __syncthreads();
+    block_scan(pl->aoff, nc, sh);
+    // splits, items (in rank order), partial rows (in cluster order)
+    for (int r = threadIdx.x; r < nc; r += kBThreads) {
+        const int c = ord[r];
+        const int64_t na = pl->nact[c], nn = off[c + 1] - off[c];
+        const int64_t tiles = (na + kFBlock - 1) / kFBlock;
+        int64_t sp = tiles > 0 ? (target_items + tiles - 1) / tiles : 0;
+        const int64_t sp_max = nn / 512 > 1 ? nn / 512 : 1;
+        sp = sp < 1 ? 1 : (sp > sp_max ? sp_max : sp);
+        int64_t jc = (nn + sp - 1) / sp;
+        jc = (jc + kMixedChunk - 1) / kMixedChunk * kMixedChunk;
+        sp = (nn + jc - 1) / jc;
+        pl->split[c] = int32_t(sp);
+        pl->jchunk[c] = jc;
+        pl->ioff[r] = tiles * sp;
+        pl->poff[c] = sp * na * ncomp;
+    }
+    __syncthreads();
+    block_scan(pl->ioff, nc, sh);
+    block_scan(pl->poff, nc, sh);
+    // global block offsets of the active lists
+    for (int c = threadIdx.x; c < nc; c += kBThreads)
+        for (int b = 0; b < nb; ++b) boff[int64_t(c) * nb + b] += pl->aoff[c];
+    if (threadIdx.x == 0) {
+        pl->queue = 0;
+        int64_t inter = 0, live = 0;
+        for (int c = 0; c < nc; ++c) {
+            inter += pl->nact[c] * (off[c + 1] - off[c]);
+            live += pl->nact[c] > 0 ? 1 : 0;
+        }
+        pl->n_live = live;
+        ctr->interactions += inter;
+        ctr->sum_n_act += pl->aoff[nc];
+        ctr->steps += 1;
+    }
+}
+
+// Ordered active lists: block (b, c) writes its actives at boff[c][b].
+__global__ void __launch_bounds__(kBThreads)
+k_b_compact(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+            int nb, const int64_t *__restrict__ tnext, const int64_t *__restrict__ boff, int all_active,
+            const BatchPlan *__restrict__ pl, int32_t *__restrict__ act)
+{
+    __shared__ int s[kBThreads];
+    constexpr int PER = kBBlock / kBThreads;
+    const int c = blockIdx.y, b = blockIdx.x;
+    const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
+    const int64_t tn = tnext[c];
+    const bool live = pl->nact[c] > 0;
+    const int64_t base = lo + int64_t(threadIdx.x) * PER;
+    int flags[PER];
+    int k0 = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k;
+        flags[k] = (live && i < hi && (all_active || b_next(t_tick, level, i) == tn)) ? 1 : 0;
+        k0 += flags[k];
+    }
+    s[threadIdx.x] = k0;
+    __syncthreads();
+    for (int o = 1; o < kBThreads; o <<= 1) {
+        const int add = int(threadIdx.x) >= o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t pos = boff[int64_t(c) * nb + b] + s[threadIdx.x] - k0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        if (flags[k]) act[pos++] = int32_t(base + k);
+}
+
+__device__ __forceinline__ int find_cluster(const int64_t *__restrict__ off, int nc, int64_t i)
+{
+    int lo = 0, hi = nc;   // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_b_cid(const int64_t *__restrict__ off, int nc, int64_t n, int32_t *__restrict__ cid)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) cid[i] = find_cluster(off, nc, i);
+}
+
+template <int P, int PREC>
+__global__ void __launch_bounds__(256)
+k_b_predict(int64_t n, const int32_t *__restrict__ cid, const int64_t *__restrict__ tnext,
+            const BatchPlan *__restrict__ pl,
+            const double *__restrict__ m, const double *__restrict__ x, const double *__restrict__ v,
+            const double *__restrict__ d0, const double *__restrict__ d1, const double *__restrict__ d2,
+            const double *__restrict__ d3, const double *__restrict__ d4, const double *__restrict__ d5,
+            const int64_t *__restrict__ t_tick, void *__restrict__ rec_out)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cid[i];
+    if (pl->nact[c] == 0) return;   // resting cluster: its records are not read
+    const double dt = double(tnext[c] - t_tick[i]) * (1.0 / double(kTicksPerUnit));
+    const double *ds[6] = {d0, d1, d2, d3, d4, d5};
+    predict_one<P, PREC>(n, i, dt, m, x, v, ds, rec_out);
+}
+
+// Persistent force kernel.  Each workgroup takes items from the queue until
+// it is empty; item r (in cluster rank order) is (cluster ord[rank], i-tile,
+// j-split).  Every wave reaches the exit: the queue only grows.
+template <class Pol, int P>
+__global__ void __launch_bounds__(kFBlock)
+k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
+          int nc, const int32_t *__restrict__ act, BatchPlan *__restrict__ pl, double eps2, int64_t n_hard,
+          int ncomp, double *__restrict__ part)
+{
+    using Rec = typename Pol::Rec;
+    using ET = typename Pol::ET;
+    __shared__ Rec tile[2][kFTile];
+    __shared__ int64_t s_item;
+    const ET e2 = ET(eps2);
+    const int64_t total = pl->ioff[nc];
+    for (;;) {
+        __syncthreads();   // previous item's tiles and s_item no longer read
+        if (threadIdx.x == 0) s_item = int64_t(atomicAdd(&pl->queue, 1ull));
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        // rank of the item's cluster: ioff[rank] <= item < ioff[rank + 1]
+        int lo = 0, hi = nc;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (pl->ioff[mid] <= item) lo = mid; else hi = mid;
+        }
+        const int c = ord[lo];
+        const int64_t local = item - pl->ioff[lo];
+        const int sp = pl->split[c];
+        const int64_t tile_i = local / sp, split = local % sp;
+        const int64_t na = pl->nact[c], base = off[c], nn = off[c + 1] - base;
+        const int64_t jc = pl->jchunk[c];
+        const int64_t j0 = base + split * jc;
+        const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
+        const int64_t nh = n_hard < nn ? n_hard : nn;
+        // this lane's active row
+        const int64_t q0 = tile_i * kFBlock + threadIdx.x;
+        const int64_t q = q0 < na ? q0 : na - 1;
+        const int32_t *al = act + pl->aoff[c];
+        typename Pol::I ip[1];
+        int64_t iidx[1];
+        double acc[1][13];
+        {
+            const int64_t ia = al[q];
+            iidx[0] = (ia >= base && ia < base + nn) ? ia : base;
+            ip[0] = Pol::load(rec[iidx[0]]);
+#pragma unroll
+            for (int cc = 0; cc < 13; ++cc) acc[0][cc] = 0.0;
+        }
+        hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
+        const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
+        lds_tiles<Pol, 1, kFBlock, 2, kFTile>(rec, js0, j1, e2, ip, tile, acc);
+        if (q0 < na) {
+            double *dst = part + pl->poff[c] + split * ncomp * na;
+#pragma unroll
+            for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + q0] = acc[0][cc];
+        }
+    }
+}
+
+// Row r of the concatenated active list: sum of its cluster's split partials
+// in split order, into outputs [3][stride] (acc, jerk, snap, crackle).
+template <int P>
+__global__ void __launch_bounds__(256)
+k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const double *__restrict__ part,
+           double *__restrict__ o0, double *__restrict__ o1, double *__restrict__ o2, double *__restrict__ o3,
+           int64_t stride)
+{
+    constexpr int NV = 3 * (P / 2);
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = pl->aoff[nc];
+    if (t >= total * NV) return;
+    const int cc = int(t / total);
+    const int64_t r = t - int64_t(cc) * total;
+    int lo = 0, hi = nc;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (pl->aoff[mid] <= r) lo = mid; else hi = mid;
+    }
+    const int64_t na = pl->nact[lo], q = r - pl->aoff[lo];
+    const double *src = part + pl->poff[lo];
+    double s = 0.0;
+    for (int sp = 0; sp < pl->split[lo]; ++sp) s += src[(int64_t(sp) * ncomp + cc) * na + q];
+    double *outs[4] = {o0, o1, o2, o3};
+    double *o = outs[cc / 3];
+    if (o) o[(cc % 3) * stride + r] = s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256)
+k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *__restrict__ cid,
+            const int64_t *__restrict__ tnext, const BatchPlan *__restrict__ pl, double *__restrict__ x,
+            double *__restrict__ v, double *__restrict__ d0, double *__restrict__ d1, double *__restrict__ d2,
+            double *__restrict__ d3, double *__restrict__ d4, double *__restrict__ d5, int64_t *__restrict__ t_tick,
+            int32_t *__restrict__ level, const double *__restrict__ force, double eta, int k_min, int k_max,
+            BatchCounters *__restrict__ ctr)
+{
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= pl->aoff[nc]) return;
+    const int64_t i = act[r];
+    if (i < 0 || i >= n) return;
+    double *dst[6] = {d0, d1, d2, d3, d4, d5};
+    const double *fnew[4] = {force, force + 3 * n, force + 6 * n, force + 9 * n};
+    const int fl = correct_one<P>(n, i, tnext[cid[i]], fnew, n, r, x, v, dst, t_tick, level, eta, k_min, k_max);
+    if (fl & 2) atomicAdd(&ctr->underflow, 1ull);
+    if (fl & 1) atomicAdd(&ctr->nonfinite, 1ull);
+}
+
+__global__ void k_b_requeue(BatchPlan *__restrict__ pl)
+{
+    if (threadIdx.x == 0) pl->queue = 0;
+}
+
+unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+template <class Pol, int P>
+hipError_t force_p(const BatchLaunch &L, const void *rec, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_b_force<Pol, P>), dim3(L.force_grid), dim3(kFBlock), 0, s,
+                       static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
+                       L.n_hard, 3 * (P / 2), L.part);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t force_prec(int precision, const BatchLaunch &L, const void *rec, hipStream_t s)
+{
+    if (precision == NBODY_MIXED) return force_p<PolMx<P, false>, P>(L, rec, s);
+    if (precision == NBODY_DS) return force_p<PolDS<P, false>, P>(L, rec, s);
+    return force_p<PolF64<P, false>, P>(L, rec, s);
+}
+
+template <int P>
+hipError_t reduce_p(const BatchLaunch &L, double *o0, double *o1, double *o2, double *o3, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_b_reduce<P>), dim3(nblk(L.n * 3 * (P / 2), 256)), dim3(256), 0, s, L.nc, L.n, L.plan,
+                       3 * (P / 2), L.part, o0, o1, o2, o3, L.n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t batch_requeue(const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_requeue, dim3(1), dim3(64), 0, s, L.plan);
+    return hipGetLastError();
+}
+
+template <class Pol, int P>
+int resident_p(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P>, kFBlock, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <int P>
+int resident_prec(int precision, int device)
+{
+    if (precision == NBODY_MIXED) return resident_p<PolMx<P, false>, P>(device);
+    if (precision == NBODY_DS) return resident_p<PolDS<P, false>, P>(device);
+    return resident_p<PolF64<P, false>, P>(device);
+}
+
+int batch_force_resident(int order, int precision, int device)
+{
+    if (order == 4) return resident_prec<4>(precision, device);
+    if (order == 6) return resident_prec<6>(precision, device);
+    return resident_prec<8>(precision, device);
+}
+
+hipError_t batch_cid(const BatchLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_cid, dim3(nblk(L.n, 256)), dim3(256), 0, s, L.off, L.nc, L.n, L.cid);
+    return hipGetLastError();
+}
+
+hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_active, int order, hipStream_t s)
+{
+    const dim3 g(unsigned(L.nb), unsigned(L.nc), 1u);
+    hipLaunchKernelGGL(k_b_min, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin);
+    hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, all_active,
+                       L.plan, L.tnext, L.bcnt);
+    hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.nb, L.off, L.ord, L.tnext, L.bcnt, L.boff,
+                       L.plan, 3 * (order / 2), L.target_items, L.ctr);
+    hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.boff,
+                       all_active, L.plan, L.act);
+    return hipGetLastError();
+}
+
+hipError_t batch_predict(const BatchLaunch &L, const nbody_state &st, int order, int precision, void *rec,
+                         hipStream_t s)
+{
+    const unsigned g = nblk(L.n, 256);
+#define NB_BP(P, PREC)                                                                                       \
+    hipLaunchKernelGGL((k_b_predict<P, PREC>), dim3(g), dim3(256), 0, s, L.n, L.cid, L.tnext, L.plan, st.m, st.x, st.v, \
+                       st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, rec)
+#define NB_BP_P(P)                                          \
+    if (precision == NBODY_FP64) NB_BP(P, NBODY_FP64);     \
+    else NB_BP(P, NBODY_MIXED)
+    if (order == 4) { NB_BP_P(4); }
+    else if (order == 6) { NB_BP_P(6); }
+    else { NB_BP_P(8); }
+#undef NB_BP_P
+#undef NB_BP
+    return hipGetLastError();
+}
+
+hipError_t batch_force(const BatchLaunch &L, int order, int precision, const void *rec, hipStream_t s)
+{
+    if (order == 4) return force_prec<4>(precision, L, rec, s);
+    if (order == 6) return force_prec<6>(precision, L, rec, s);
+    return force_prec<8>(precision, L, rec, s);
+}
+
+hipError_t batch_reduce(const BatchLaunch &L, int order, double *o0, double *o1, double *o2, double *o3,
+                        hipStream_t s)
+{
+    if (order == 4) return reduce_p<4>(L, o0, o1, o2, o3, s);
+    if (order == 6) return reduce_p<6>(L, o0, o1, o2, o3, s);
+    return reduce_p<8>(L, o0, o1, o2, o3, s);
+}
+
+hipError_t batch_correct(const BatchLaunch &L, const nbody_config &c, const nbody_state &st, hipStream_t s)
+{
+    const unsigned g = nblk(L.n, 256);
+#define NB_BC(P)                                                                                              \
+    hipLaunchKernelGGL((k_b_correct<P>), dim3(g), dim3(256), 0, s, L.n, L.nc, L.act, L.cid, L.tnext, L.plan,     \
+                       st.x, st.v, st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, st.level,    \
+                       L.force, c.eta, int(c.k_min), int(c.k_max), L.ctr)
+    if (c.order == 4) NB_BC(4);
+    else if (c.order == 6) NB_BC(6);
+    else NB_BC(8);
+#undef NB_BC
+    return hipGetLastError();
+}
+
+}  // namespace nb

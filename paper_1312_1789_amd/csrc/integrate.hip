@@ -243,17 +243,17 @@ k_sched_compact(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__
 // FP64 energy: per block, sum over its i of m_i v_i^2 and of
 // m_i sum_{j != i} m_j / sqrt(r_ij^2 + eps_ij^2); fixed-order tree in LDS.
 __global__ void __launch_bounds__(256)
-k_energy(int64_t n, int64_t n_hard, double eps2, const double *__restrict__ m, const double *__restrict__ x,
+k_energy(int64_t n, int64_t stride, int64_t n_hard, double eps2, const double *__restrict__ m, const double *__restrict__ x,
          const double *__restrict__ v, double *__restrict__ partial)
 {
     __shared__ double sk[256], sw[256];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t ii = i < n ? i : n - 1;
-    const double xi = x[ii], yi = x[n + ii], zi = x[2 * n + ii];
+    const double xi = x[ii], yi = x[stride + ii], zi = x[2 * stride + ii];
     double w = 0.0;
     const int64_t jh = n_hard < n ? n_hard : n;
     for (int64_t j = 0; j < jh; ++j) {
-        const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
+        const double dx = x[j] - xi, dy = x[stride + j] - yi, dz = x[2 * stride + j] - zi;
         const double e = ii < n_hard ? 0.0 : eps2;
         double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e)));
         const bool ok = j != ii;
@@ -261,12 +261,12 @@ k_energy(int64_t n, int64_t n_hard, double eps2, const double *__restrict__ m, c
         w += ok ? m[j] * rsqrt64(r2) : 0.0;
     }
     for (int64_t j = jh; j < n; ++j) {
-        const double dx = x[j] - xi, dy = x[n + j] - yi, dz = x[2 * n + j] - zi;
+        const double dx = x[j] - xi, dy = x[stride + j] - yi, dz = x[2 * stride + j] - zi;
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
         w += m[j] * rsqrt64(r2);
     }
     if (ii >= jh) w -= m[ii] * rsqrt64(eps2);   // self pair of the softened loop
-    const double vx = v[ii], vy = v[n + ii], vz = v[2 * n + ii];
+    const double vx = v[ii], vy = v[stride + ii], vz = v[2 * stride + ii];
     sk[threadIdx.x] = i < n ? m[ii] * __builtin_fma(vx, vx, __builtin_fma(vy, vy, vz * vz)) : 0.0;
     sw[threadIdx.x] = i < n ? m[ii] * w : 0.0;
     __syncthreads();
@@ -395,12 +395,12 @@ hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_energy(int64_t n, int64_t n_hard, double eps2, const double *m, const double *x,
+hipError_t launch_energy(int64_t n, int64_t stride, int64_t n_hard, double eps2, const double *m, const double *x,
                          const double *v, double *partials, int *n_partials, hipStream_t s)
 {
     const unsigned g = blocks_for(n, 256);
     *n_partials = int(g);
-    hipLaunchKernelGGL(k_energy, dim3(g), dim3(256), 0, s, n, n_hard, eps2, m, x, v, partials);
+    hipLaunchKernelGGL(k_energy, dim3(g), dim3(256), 0, s, n, stride, n_hard, eps2, m, x, v, partials);
     return hipGetLastError();
 }
 

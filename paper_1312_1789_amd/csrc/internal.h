@@ -10,6 +10,19 @@
 
 namespace nb {
 
+// Record an error message (thread-local, returned by nbody_last_error) and
+// return s.
+nbody_status fail(nbody_status s, const char *fmt, ...);
+const char *last_error();
+// Validate a configuration (records the message on failure).
+nbody_status check_config_checked(const nbody_config *c);
+
+#define NB_HIP(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return nb::fail(NBODY_E_HIP, "%s: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
 constexpr int kLevelMax = 20;               // time tick = 2^-20 time units
 constexpr int64_t kTicksPerUnit = int64_t(1) << kLevelMax;
 constexpr int kSchedBlock = 256;            // threads per scheduler block
@@ -89,7 +102,8 @@ hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *leve
 hipError_t launch_init_levels(const nbody_config &c, const nbody_state &st, const double *a, const double *j,
                               hipStream_t s);
 
-hipError_t launch_energy(int64_t n, int64_t n_hard, double eps2, const double *m, const double *x,
+// Energy partials of n particles whose [3][.] arrays have row stride `stride`.
+hipError_t launch_energy(int64_t n, int64_t stride, int64_t n_hard, double eps2, const double *m, const double *x,
                          const double *v, double *partials, int *n_partials, hipStream_t s);
 
 }  // namespace nb

@@ -149,3 +149,109 @@ class Simulation:
             self.d[k].copy_(_dev(np.asarray(a).reshape(3, self.n), torch.float64, self.device))
         self.t_tick.copy_(_dev(t_tick, torch.int64, self.device))
         self.level.copy_(_dev(level, torch.int32, self.device))
+
+
+class Batch:
+    """Many independent clusters advanced together through the batched
+    entry points.  ``clusters`` is a list of (m, x, v) host arrays; the
+    device state is their concatenation (cluster c owns [off[c], off[c+1])),
+    with the same tensors as Simulation.  Runs on its own (default-priority)
+    stream so that one batched step can be captured in a HIP graph."""
+
+    def __init__(self, clusters, order: int = 6, precision: str | int = "mixed", eps2: float = 1e-8,
+                 n_hard: int = 0, eta: float = 0.1, eta_start: float = 0.01, k_min: int = 3, k_max: int = 20,
+                 device: str = "cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the N-body library runs only on the device")
+        self.device = torch.device(device)
+        self.order = int(order)
+        prec = abi.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        sizes = [int(np.asarray(c[0]).shape[0]) for c in clusters]
+        self.off = [0] + list(np.cumsum(sizes).astype(int))
+        self.nc = len(sizes)
+        n = self.off[-1]
+        self.n = n
+        self.cfg = abi.nbody_config(self.order, prec, n, int(n_hard), float(eps2), float(eta), float(eta_start),
+                                    int(k_min), int(k_max))
+        self.stream = torch.cuda.Stream(self.device)
+        m = np.concatenate([np.asarray(c[0], dtype=np.float64) for c in clusters])
+        x = np.concatenate([np.asarray(c[1], dtype=np.float64).reshape(3, -1) for c in clusters], axis=1)
+        v = np.concatenate([np.asarray(c[2], dtype=np.float64).reshape(3, -1) for c in clusters], axis=1)
+        self.m = _dev(m, torch.float64, self.device)
+        self.x = _dev(x, torch.float64, self.device)
+        self.v = _dev(v, torch.float64, self.device)
+        self.d = [torch.zeros((3, n), dtype=torch.float64, device=self.device) for _ in range(self.order - 2)]
+        self.t_tick = torch.zeros(n, dtype=torch.int64, device=self.device)
+        self.level = torch.zeros(n, dtype=torch.int32, device=self.device)
+        nbytes = abi.nbody_batch_workspace_size(self.cfg, self.off)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(self.device)   # state tensors written before the batch stream reads them
+        self.b = abi.nbody_batch_create(self.cfg, self.off, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        ds = [t.data_ptr() for t in self.d] + [None] * (6 - len(self.d))
+        self.state = abi.nbody_state(self.m.data_ptr(), self.x.data_ptr(), self.v.data_ptr(),
+                                     (abi.C.c_void_p * 6)(*ds), self.t_tick.data_ptr(), self.level.data_ptr())
+
+    def close(self):
+        if getattr(self, "b", 0):
+            self.stream.synchronize()
+            abi.nbody_batch_destroy(self.b)
+            self.b = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, force_grid: int = 0, target_items: int = 0):
+        abi.nbody_batch_set_launch(self.b, force_grid, target_items)
+
+    def set_end(self, t_end_tick: int):
+        abi.nbody_batch_set_end(self.b, t_end_tick)
+
+    def init(self):
+        abi.nbody_batch_init(self.b, self.state)
+
+    def step(self, k: int = 1):
+        abi.nbody_batch_step(self.b, self.state, k)
+
+    def capture(self):
+        abi.nbody_batch_capture(self.b, self.state)
+
+    def replay(self, k: int = 1):
+        abi.nbody_batch_replay(self.b, k)
+
+    def poll(self):
+        return abi.nbody_batch_poll(self.b, self.nc)
+
+    def last_step(self):
+        """(aoff list, act int32 tensor, forces (order/2, 3, n_act) tensor)."""
+        aoff = abi.nbody_batch_last_step(self.b, self.nc)
+        na = aoff[-1]
+        act = torch.empty(max(na, 1), dtype=torch.int32, device=self.device)
+        f = torch.empty((self.order // 2, 3, max(na, 1)), dtype=torch.float64, device=self.device)
+        abi.nbody_batch_last_step(self.b, self.nc, act.data_ptr(), f.data_ptr())
+        return aoff, act[:na], f[:, :, :na]
+
+    def energy(self):
+        return abi.nbody_batch_energy(self.b, self.state, self.nc)
+
+    def stats(self) -> abi.nbody_stats:
+        return abi.nbody_batch_get_stats(self.b)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def to_numpy(self) -> dict:
+        self.stream.synchronize()
+        return {"m": self.m.cpu().numpy(), "x": self.x.cpu().numpy(), "v": self.v.cpu().numpy(),
+                "d": [t.cpu().numpy() for t in self.d], "t_tick": self.t_tick.cpu().numpy(),
+                "level": self.level.cpu().numpy()}
+
+    def cluster(self, h: dict, c: int) -> dict:
+        """Cluster c's slice of a to_numpy() dict."""
+        a, b = self.off[c], self.off[c + 1]
+        return {"m": h["m"][a:b], "x": h["x"][:, a:b].copy(), "v": h["v"][:, a:b].copy(),
+                "d": [t[:, a:b].copy() for t in h["d"]], "t_tick": h["t_tick"][a:b].copy(),
+                "level": h["level"][a:b].copy()}

@@ -71,3 +71,43 @@ def test_null_context_is_rejected():
     assert L.nbody_step(None, None, None, None) == abi.NBODY_E_INVALID
     assert L.nbody_set_launch(None, 1, 256, 0, 0) == abi.NBODY_E_INVALID
     assert L.nbody_get_predicted(None, None, None, None, None) == abi.NBODY_E_INVALID
+
+
+def test_batch_workspace_size():
+    off = [0, 1000, 3000, 3002]
+    a = abi.nbody_batch_workspace_size(_cfg(n=3002), off)
+    b = abi.nbody_batch_workspace_size(_cfg(n=6002), off[:-1] + [3002, 6002])
+    assert b > a > 0
+
+
+@pytest.mark.parametrize("off,kw", [
+    ([0, 1000, 999], dict(n=999)),           # decreasing offsets
+    ([0, 1, 1000], dict(n=1000)),            # a one-particle cluster
+    ([1, 500, 1000], dict(n=1000)),          # off[0] != 0
+    ([0, 500, 1000], dict(n=1001)),          # last offset != n
+    ([0, 500, 1000], dict(n=1000, n_hard=501)),   # n_hard beyond a cluster
+    ([0, 500, 1000], dict(n=1000, order=7)),
+    ([0], dict(n=1000)),                     # no clusters
+])
+def test_batch_validation(off, kw):
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_batch_workspace_size(_cfg(**kw), off)
+    assert e.value.status == abi.NBODY_E_INVALID
+    assert abi.last_error()
+
+
+def test_batch_too_uneven_is_unsupported():
+    # one cluster of 2^23 and 65534 pairs: 8192 scheduling blocks x 65535 cells
+    off = [0, 1 << 23] + [(1 << 23) + 2 * (k + 1) for k in range(65534)]
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_batch_workspace_size(_cfg(n=off[-1]), off)
+    assert e.value.status == abi.NBODY_E_UNSUPPORTED
+
+
+def test_batch_null_handles_are_rejected():
+    L = abi.lib()
+    assert L.nbody_batch_destroy(None) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_step(None, None, 1) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_replay(None, 1) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_set_launch(None, 0, 0) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_poll(None, None, None) == abi.NBODY_E_INVALID

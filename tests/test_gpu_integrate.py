@@ -13,7 +13,7 @@ import torch
 
 import nbody_ics
 import oracle
-from helpers import TICKS, err_stats, rel_err, say
+from helpers import TICKS, compare_corrected, err_stats, oracle_correct, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -112,79 +112,6 @@ def test_init_parity(order):
     assert np.sum(got["level"] != os_.level) <= 2
 
 
-def _oracle_correct(ocfg, os0, act, T, F):
-    """Oracle corrector, interpolation and level for the active list, composed
-    from the oracle's per-component routines.  Also returns, per active row,
-    the rounding scale of each interpolated derivative (sum of |coefficient x
-    input|; the interpolation cancels heavily for short steps) and the
-    distance of log2(dt_crit) from the nearest integer."""
-    p, q = ocfg.order, ocfg.order // 2
-    newd = [F["acc"], F["jrk"], F["snp"], F["crk"]]
-    x, v = os0.x.copy(), os0.v.copy()
-    d = [a.copy() for a in os0.d]
-    lv = os0.level.copy()
-    scale = np.zeros((p - q, 3, act.size))
-    margin = np.zeros(act.size)
-    dnorm = np.zeros((p, act.size))
-    mats = {}
-    for r, i in enumerate(act):
-        h = (T - os0.t_tick[i]) / TICKS
-        if h not in mats:
-            eye = np.eye(2 * q)
-            mats[h] = np.stack([oracle.hermite_high(p, h, eye[k, :q], eye[k, q:]) for k in range(2 * q)], axis=1)
-        M = mats[h]
-        Dall = np.zeros((p, 3))
-        for c in range(3):
-            D0 = [os0.d[k][c, i] for k in range(q)]
-            D1 = [newd[k][c, r] for k in range(q)]
-            x[c, i], v[c, i] = oracle.hermite_correct(p, h, os0.x[c, i], os0.v[c, i], D0, D1)
-            Dall[:q, c] = D1
-            Dall[q:, c] = oracle.hermite_high(p, h, D0, D1)
-            scale[:, c, r] = np.abs(M) @ np.abs(np.concatenate([D0, D1]))
-        for k in range(p - 2):
-            d[k][:, i] = Dall[k]
-        dnorm[:, r] = np.linalg.norm(Dall, axis=1)
-        dtc = oracle.dt_crit(p, ocfg.eta, dnorm[:, r])
-        lv[i] = oracle.new_level(dtc, int(os0.level[i]), T, ocfg.k_min, ocfg.k_max)
-        margin[r] = abs(np.log2(dtc) - np.round(np.log2(dtc)))
-    return x, v, d, lv, scale, margin, dnorm
-
-
-def _compare_corrected(got, want, act, order, rel_force_err, tag):
-    """x, v to FP64 rounding; interpolated derivatives within their rounding
-    scale (amplified by the force difference); levels equal except where
-    log2(dt_crit) lies within its own rounding uncertainty of an integer
-    (the highest interpolated derivatives cancel heavily for short steps)."""
-    x, v, d, lv, scale, margin, dnorm = want
-    q = order // 2
-    # relative uncertainty of each interpolated |a^(k)| from its rounding
-    # scale, carried into log2(dt_crit): the criterion uses a^(p-3..p-1)
-    # (order 4: a^(2), a^(3)) under a 1/(p-3) power (order 4: a square root)
-    unc = (512 * 2.0 ** -53 + rel_force_err) * np.linalg.norm(scale, axis=1) / np.maximum(dnorm[q:], 1e-300)
-    ks = [2, 3] if order == 4 else list(range(order - 3, order))
-    root = 2.0 if order == 4 else float(order - 3)
-    margin_tol = 4.0 * sum(unc[k - q] for k in ks if k >= q) / root / np.log(2.0) + 1e-12
-    for name, g, w in [("x", got["x"], x), ("v", got["v"], v)]:
-        st = err_stats(rel_err(g[:, act], w[:, act]))
-        say("%s order %d %s rms %.2e max %.2e" % (tag, order, name, st["rms"], st["max"]))
-        assert st["max"] <= 1e-12
-    for k in range(order - 2):
-        diff = np.abs(got["d"][k][:, act] - d[k][:, act])
-        if k < q:
-            bound = 1e-13 * np.abs(d[k][:, act]) + 1e-300 if rel_force_err == 0 else \
-                rel_force_err * np.linalg.norm(d[k][:, act], axis=0)
-        else:
-            bound = (512 * 2.0 ** -53 + rel_force_err) * scale[k - q]
-        ratio = float(np.max(diff / np.maximum(bound, 1e-300)))
-        say("%s order %d d[%d] max |diff| / bound %.2e" % (tag, order, k, ratio))
-        assert ratio <= 1.0, (k, ratio)
-    mism = np.nonzero(got["level"][act] != lv[act])[0]
-    say("%s order %d level mismatches %d of %d (margins %s, allowed %s)"
-        % (tag, order, mism.size, act.size, margin[mism], margin_tol[mism]))
-    assert np.all(margin[mism] < margin_tol[mism])
-    assert np.all(np.abs(got["level"][act].astype(int) - lv[act].astype(int)) <= 1)
-
-
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_correct_parity(order):
     """Identical old state, identical new forces: corrected state,
@@ -206,7 +133,7 @@ def test_correct_parity(order):
     sim.correct(torch.as_tensor(act, device=dev), T, f)
     got = sim.to_numpy()
     assert np.all(got["t_tick"][act] == T)
-    _compare_corrected(got, _oracle_correct(ocfg, os0, act, T, F), act, order, 0.0, "correct")
+    compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, 0.0, "correct")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -233,10 +160,10 @@ def test_step_parity(order, precision):
         got = sim.to_numpy()
         assert np.all(got["t_tick"][act] == T)
         if precision == "fp64":
-            _compare_corrected(got, _oracle_correct(ocfg, os0, act, T, F), act, order, rel_force, "step")
+            compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, rel_force, "step")
         else:
             # MIXED: the corrected state differs by the force error times h
-            want = _oracle_correct(ocfg, os0, act, T, F)
+            want = oracle_correct(ocfg, os0, act, T, F)
             st = err_stats(rel_err(got["v"][:, act] - os0.v[:, act], want[1][:, act] - os0.v[:, act]))
             say("step order %d mixed dv rms %.2e max %.2e" % (order, st["rms"], st["max"]))
             assert st["rms"] <= 2e-5
