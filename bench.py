@@ -10,6 +10,13 @@ level (k_min = k_max = 10), so each step has N_act = N and does N_act * N =
 second of the whole step, MIXED force precision, with the FP64 force timed
 beside it and the error of both against the CPU oracle on a sample of rows.
 
+A second workload, --workload batched, advances 256 independent Plummer
+clusters (N_c = round(2^U(10, 16)), 6th order, MIXED, eta = 0.1) by the same
+number of block steps per cluster twice: through the batched entry points
+(one captured HIP graph per batched step, replayed) and with one context per
+cluster (one nbody_step per cluster and block step).  Metric: aggregate pair
+interactions per second of each.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -152,8 +159,158 @@ def cpu_baseline_and_error(model, sims, order, target_s):
     return base, errors, rows
 
 
+BATCH_METRIC = "aggregate pair interactions/s, 256 batched Plummer clusters, 6th order, mixed"
+
+
+def batched_clusters(n_clusters: int, seed: int = 1400):
+    """Cluster sizes round(2^U(10, 16)) from one seeded draw; cluster c is a
+    Plummer model with seed seed + c."""
+    import nbody_ics
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.round(2.0 ** rng.uniform(10.0, 16.0, n_clusters)).astype(int)
+    return [nbody_ics.plummer(int(s), seed + c) for c, s in enumerate(sizes)]
+
+
+def run_batched(args):
+    import torch
+    from paper_1312_1789_amd import Batch, Simulation
+    t0 = time.perf_counter()
+    models = batched_clusters(args.clusters)
+    sizes = [m.n for m in models]
+    log("workload: %d Plummer clusters, n total %d (min %d, max %d), %.1f s to generate"
+        % (len(models), sum(sizes), min(sizes), max(sizes), time.perf_counter() - t0))
+    kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
+    clusters = [(m.m, m.x, m.v) for m in models]
+    B = Batch(clusters, precision="mixed", **kw)
+    if args.batch_target or args.batch_grid or args.batch_itile:
+        B.set_launch(args.batch_grid, args.batch_target, args.batch_itile)
+    t0 = time.perf_counter()
+    B.init()
+    B.synchronize()
+    log("[batched] init %.2f s" % (time.perf_counter() - t0))
+    # start-up transient: every cluster to t_warm (all particles synchronised there)
+    t_warm = int(args.warm_time * 2 ** 20)
+    B.set_end(t_warm)
+    B.capture()
+    t0 = time.perf_counter()
+    replays = 0
+    while True:
+        B.replay(64)
+        replays += 64
+        live, tcur = B.poll()
+        if live == 0:
+            break
+        if replays % 1024 == 0:
+            log("[batched] warm-up replay %d: %d clusters live, min time %.5f" % (replays, live, min(tcur) / 2.0 ** 20))
+    log("[batched] warm-up to t = %.4f: %d replays, %.1f s" % (t_warm / 2.0 ** 20, replays, time.perf_counter() - t0))
+    B.set_end(1 << 62)
+    tuned = None
+    if args.autotune_steps > 0:
+        t0 = time.perf_counter()
+        B.autotune(args.autotune_steps)
+        tuned = B.get_launch()
+        log("[batched] autotune (%d steps per shape): force_grid %d, target_items %d, i_tile %d, %.1f s"
+            % (args.autotune_steps, tuned[0], tuned[1], tuned[2], time.perf_counter() - t0))
+    shape = B.get_launch()
+    h = B.to_numpy()   # the common starting state of the three timed runs
+    B.capture()
+    B.replay(args.warmup)
+    B.synchronize()
+    s0 = B.stats()
+    t0 = time.perf_counter()
+    B.replay(args.steps)
+    B.synchronize()
+    wall = time.perf_counter() - t0
+    s1 = B.stats()
+    inter = s1.interactions - s0.interactions
+    nact = (s1.sum_n_act - s0.sum_n_act) / args.steps
+    live, tcur = B.poll()
+    log("[batched] %d graph replays: %.3f ms/replay, %.4e interactions/s, mean active %.0f per replay, "
+        "cluster times %.4f..%.4f" % (args.steps, wall / args.steps * 1e3, inter / wall, nact,
+                                      min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20))
+    batched = {"interactions_per_s": inter / wall, "ms_per_batched_step": wall / args.steps * 1e3,
+               "interactions": inter, "mean_active_per_batched_step": nact,
+               "launch": {"force_grid": shape[0], "target_items": shape[1], "i_tile": shape[2]},
+               "cluster_time_range": [min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20]}
+    del B
+    # the same steps launched eagerly (no graph)
+    E = Batch(clusters, precision="mixed", **kw)
+    E.set_launch(0, shape[1], shape[2])
+    E.load_state(h)
+    E.step(args.warmup)
+    E.synchronize()
+    e0 = E.stats()
+    t0 = time.perf_counter()
+    E.step(args.steps)
+    E.synchronize()
+    ewall = time.perf_counter() - t0
+    e1 = E.stats()
+    log("[batched eager] %.3f ms/step, %.4e interactions/s" % (ewall / args.steps * 1e3,
+                                                              (e1.interactions - e0.interactions) / ewall))
+    eager = {"interactions_per_s": (e1.interactions - e0.interactions) / ewall,
+             "ms_per_batched_step": ewall / args.steps * 1e3}
+    del E
+    # one context per cluster, the same number of block steps each, same start
+    tot_inter, tot_wall, tot_steps = 0.0, 0.0, 0
+    for c, m in enumerate(models):
+        sim = Simulation(m.m, m.x, m.v, precision="mixed", **kw)
+        a, b = sum(sizes[:c]), sum(sizes[:c + 1])
+        sim.load_state(h["x"][:, a:b], h["v"][:, a:b], [d[:, a:b] for d in h["d"]], h["t_tick"][a:b],
+                       h["level"][a:b])
+        for _ in range(args.warmup):
+            sim.step()
+        torch.cuda.synchronize()
+        a0 = sim.stats().interactions
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sim.step()
+        torch.cuda.synchronize()
+        tot_wall += time.perf_counter() - t0
+        tot_inter += sim.stats().interactions - a0
+        tot_steps += args.steps
+        if c % 32 == 31:
+            log("[per-cluster] %d clusters done, %.1f s timed" % (c + 1, tot_wall))
+        sim.close()
+        del sim
+    log("[per-cluster] %d steps over %d contexts: %.1f s, %.4e interactions/s"
+        % (tot_steps, len(models), tot_wall, tot_inter / tot_wall))
+    per_cluster = {"interactions_per_s": tot_inter / tot_wall, "seconds": tot_wall, "interactions": tot_inter}
+    line = {
+        "metric": BATCH_METRIC,
+        "value": batched["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": batched["ms_per_batched_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%d Plummer clusters, N_c = round(2^U(10,16)) (seed 1400 + c), n = %d, 6th-order "
+                               "Hermite block steps, MIXED force, eta = 0.1, eps = 1e-4, from t = %.4f; one batched "
+                               "step = one block step of every cluster" % (len(models), sum(sizes),
+                                                                            t_warm / 2.0 ** 20),
+                   "n": sum(sizes), "clusters": len(models), "order": 6, "precision": "mixed"},
+        "autotuned": tuned is not None,
+        "batched_graph": batched,
+        "batched_eager": eager,
+        "one_context_per_cluster": per_cluster,
+        "graph_over_per_cluster": batched["interactions_per_s"] / per_cluster["interactions_per_s"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--workload", choices=["king1m", "batched"], default="king1m")
+    ap.add_argument("--clusters", type=int, default=256)
+    ap.add_argument("--batch-target", type=int, default=0, help="work items aimed for per cluster (0 = default)")
+    ap.add_argument("--batch-grid", type=int, default=0, help="persistent force workgroups (0 = resident)")
+    ap.add_argument("--batch-itile", type=int, default=0, help="active rows per work item, 64 or 256 (0 = default)")
+    ap.add_argument("--warm-time", type=float, default=1.0 / 64, help="batched: integrate to this time first")
+    ap.add_argument("--autotune-steps", type=int, default=2, help="batched: steps per autotuned shape (0 = off)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -186,6 +343,9 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read + %d MiB written" % (args.calibrate_copy_mib, args.calibrate_copy_mib))
         del src, dst
+    if args.workload == "batched":
+        run_batched(args)
+        return
 
     t0 = time.perf_counter()
     model = nbody_ics.king(args.n, 7.0, 13)

@@ -72,6 +72,14 @@ typedef struct {
     double eta_start;   /* initial step: dt0 = eta_start |a| / |jerk| */
     int32_t k_min;      /* largest step 2^-k_min */
     int32_t k_max;      /* smallest step 2^-k_max, k_min <= k_max <= 20 */
+    int32_t dt_rule;    /* time-step criterion at orders 6 and 8 (order 4 always uses Aarseth's):
+                           1 = generalised Aarseth criterion of the scheme's order,
+                           dt = eta (A_1 / A_(p-2))^(1/(p-3)), A_k = sqrt(|a^(k-1)||a^(k+1)|) + |a^(k)|;
+                           2 = its order-4 form dt = eta A_1 / A_2 (reads a .. a^(3) only);
+                           0 = 2 for MIXED / DS or order 8, else 1.  The full-order form
+                           reads derivatives interpolated with weights ~ h^-(p-1); their
+                           rounding noise (FP32 force terms, or FP64 at order 8) makes dt_crit
+                           collapse to 2^-k_max at short steps. */
 } nbody_config;
 
 /* Particle state, DEVICE pointers, caller-owned, 8-byte aligned.
@@ -248,9 +256,23 @@ nbody_status nbody_batch_energy(nbody_batch *b, const nbody_state *state, double
 nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out);
 
 /* Persistent force launch: force_grid workgroups (0 = as many as fit on the
- * device at once) and target_items work items aimed for per cluster when its
- * active set is small (1..64, 0 = 16; the j-range is split to reach it). */
-nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items);
+ * device at once), target_items work items aimed for per cluster when its
+ * active set is small (1..64, 0 = 16; the j-range is split to reach it) and
+ * i_tile active rows per work item (64 or 256, 0 = 64).  Applies to later
+ * steps and captures (a captured graph keeps the shape it was captured with).
+ * Results depend on the shape only through the FP64 summation order of the
+ * split partials (and, in MIXED mode, where the FP32 chunks start). */
+nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items, int32_t i_tile);
+
+/* The shape in use (HOST out[3]): force_grid, target_items, i_tile. */
+nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3]);
+
+/* Autotuner: times `steps` batched steps (after one untimed step) for each
+ * i_tile in {64, 256} and target_items in {4, 8, 16, 32, 64} with HIP events,
+ * and keeps the shape with the most pair interactions per second.  The
+ * steps are real: the clusters advance by 11 * (steps + 1) batched steps
+ * (fewer where they reach t_end).  Drops a captured graph (capture again). */
+nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *state, int32_t steps);
 
 /* Message for the last non-OK status returned on this thread. */
 const char *nbody_last_error(void);

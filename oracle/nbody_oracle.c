@@ -16,7 +16,9 @@
  *   - higher derivatives at the end of a step: the unique Hermite interpolant
  *     of degree p-1 through the derivatives known at both ends;
  *   - time step: Aarseth's criterion (order 4) and its generalisation by
- *     Nitadori & Makino (2008) (orders 6 and 8);
+ *     Nitadori & Makino (2008) (orders 6 and 8), either of the scheme's order
+ *     or of order 4 (the form that reads only a .. a^(3), for forces that
+ *     carry single-precision noise);
  *   - block time steps: power-of-two steps, t_i always a multiple of dt_i,
  *     a step may double only when commensurate.
  * Build: gcc -O2 -ffp-contract=off -fopenmp, so rounding follows the source.
@@ -43,6 +45,8 @@ typedef struct {
     double eta;       /* accuracy parameter of the time-step criterion */
     double eta_start; /* initial step parameter */
     int k_min, k_max; /* levels allowed: dt in [2^-k_max, 2^-k_min] */
+    int dt_rule;      /* orders 6, 8: 1 = generalised criterion of the scheme's order,
+                         2 = its order-4 form (reads a .. a^(3) only) */
 } oracle_config;
 
 /* Particle state.  d[k] is the k-th derivative of the acceleration a^(k)
@@ -258,12 +262,15 @@ void oracle_hermite_correct(int p, double h, double x0, double v0, const double 
  *   p = 6, 8 (generalised Aarseth, Nitadori & Makino 2008):
  *       A_k = sqrt(|a^(k-1)| |a^(k+1)|) + |a^(k)|
  *       dt  = eta (A_1 / A_(p-2))^(1/(p-3))                                  */
-double oracle_dt_crit(int p, double eta, const double *F)
+double oracle_dt_crit(int p, double eta, const double *F, int rule)
 {
     if (p == 4) return sqrt(eta * (F[0] * F[2] + F[1] * F[1]) / (F[1] * F[3] + F[2] * F[2]));
+    /* generalised criterion of order q: dt = eta (A_1 / A_(q-2))^(1/(q-3)),
+     * A_k = sqrt(|a^(k-1)| |a^(k+1)|) + |a^(k)| */
+    const int q = (rule == 2) ? 4 : p;
     const double A1 = sqrt(F[0] * F[2]) + F[1];
-    const double Ak = sqrt(F[p - 3] * F[p - 1]) + F[p - 2];
-    return eta * pow(A1 / Ak, 1.0 / (double)(p - 3));
+    const double Ak = sqrt(F[q - 3] * F[q - 1]) + F[q - 2];
+    return eta * pow(A1 / Ak, 1.0 / (double)(q - 3));
 }
 
 /* Block quantisation: the largest power of two 2^-k <= dt_crit with k clamped
@@ -403,7 +410,7 @@ int64_t oracle_block_step(const oracle_config *c, oracle_state *s, int64_t *t_ne
             double w[3] = {Dall[0][l], Dall[1][l], Dall[2][l]};
             Fn[l] = norm3(w);
         }
-        const double dtc = oracle_dt_crit(p, c->eta, Fn);
+        const double dtc = oracle_dt_crit(p, c->eta, Fn, c->dt_rule);
         if (!(dtc >= ldexp(1.0, -c->k_max))) ++under;
         s->level[i] = oracle_new_level(dtc, s->level[i], t_next, c->k_min, c->k_max);
         s->t_tick[i] = t_next;

@@ -38,7 +38,7 @@ def build() -> str:
 class _Config(C.Structure):
     _fields_ = [("order", C.c_int), ("eps2", C.c_double), ("n_hard", C.c_int64),
                 ("eta", C.c_double), ("eta_start", C.c_double),
-                ("k_min", C.c_int), ("k_max", C.c_int)]
+                ("k_min", C.c_int), ("k_max", C.c_int), ("dt_rule", C.c_int)]
 
 
 class _State(C.Structure):
@@ -63,7 +63,7 @@ def _load():
         lib.oracle_hermite_high.restype = None
         lib.oracle_hermite_correct.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, P, P, P, P]
         lib.oracle_hermite_correct.restype = None
-        lib.oracle_dt_crit.argtypes = [C.c_int, C.c_double, P]
+        lib.oracle_dt_crit.argtypes = [C.c_int, C.c_double, P, C.c_int]
         lib.oracle_dt_crit.restype = C.c_double
         lib.oracle_new_level.argtypes = [C.c_double, C.c_int, C.c_int64, C.c_int, C.c_int]
         lib.oracle_init.argtypes = [C.POINTER(_Config), C.POINTER(_State)]
@@ -85,9 +85,11 @@ class OracleConfig:
     eta_start: float = 0.01
     k_min: int = 3
     k_max: int = 20
+    dt_rule: int = 1    # orders 6, 8: 1 = generalised criterion of the order, 2 = its order-4 form
 
     def _c(self) -> _Config:
-        return _Config(self.order, self.eps2, self.n_hard, self.eta, self.eta_start, self.k_min, self.k_max)
+        return _Config(self.order, self.eps2, self.n_hard, self.eta, self.eta_start, self.k_min, self.k_max,
+                       self.dt_rule)
 
 
 def _p(a: np.ndarray | None):
@@ -193,9 +195,10 @@ def hermite_correct(p: int, h: float, x0: float, v0: float, D0, D1):
     return float(x1[0]), float(v1[0])
 
 
-def dt_crit(p: int, eta: float, F) -> float:
+def dt_crit(p: int, eta: float, F, rule: int = 1) -> float:
+    """Time-step criterion from |a^(k)|, k = 0 .. p-1 (rule: see OracleConfig)."""
     F = _f64(F)
-    return float(_load().oracle_dt_crit(p, eta, _p(F)))
+    return float(_load().oracle_dt_crit(p, eta, _p(F), int(rule)))
 
 
 def new_level(dtc: float, level_old: int, t1_tick: int, k_min: int, k_max: int) -> int:

@@ -27,6 +27,14 @@ NBODY_MIXED = 1
 NBODY_DS = 2
 PRECISIONS = {"fp64": NBODY_FP64, "mixed": NBODY_MIXED, "ds": NBODY_DS}
 
+
+def effective_dt_rule(order: int, precision: int, dt_rule: int = 0) -> int:
+    """The time-step rule a configuration runs with (dt_rule 0 resolved as
+    the library resolves it)."""
+    if dt_rule:
+        return int(dt_rule)
+    return 2 if (precision != NBODY_FP64 or order == 8) else 1
+
 #: every symbol the header declares
 EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
@@ -35,6 +43,7 @@ EXPORTS = (
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
     "nbody_batch_set_end", "nbody_batch_step", "nbody_batch_capture", "nbody_batch_replay", "nbody_batch_poll",
     "nbody_batch_last_step", "nbody_batch_energy", "nbody_batch_get_stats", "nbody_batch_set_launch",
+    "nbody_batch_get_launch", "nbody_batch_autotune",
     "nbody_last_error",
 )
 
@@ -42,7 +51,7 @@ EXPORTS = (
 class nbody_config(C.Structure):
     _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("n", C.c_int64), ("n_hard", C.c_int64),
                 ("eps2", C.c_double), ("eta", C.c_double), ("eta_start", C.c_double),
-                ("k_min", C.c_int32), ("k_max", C.c_int32)]
+                ("k_min", C.c_int32), ("k_max", C.c_int32), ("dt_rule", C.c_int32)]
 
 
 class nbody_state(C.Structure):
@@ -102,7 +111,9 @@ def lib():
             "nbody_batch_last_step": [P, C.POINTER(I64), P, P],
             "nbody_batch_energy": [P, C.POINTER(nbody_state), C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "nbody_batch_get_stats": [P, C.POINTER(nbody_stats)],
-            "nbody_batch_set_launch": [P, C.c_int32, C.c_int32],
+            "nbody_batch_set_launch": [P, C.c_int32, C.c_int32, C.c_int32],
+            "nbody_batch_get_launch": [P, C.POINTER(C.c_int32)],
+            "nbody_batch_autotune": [P, C.POINTER(nbody_state), C.c_int32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -292,5 +303,17 @@ def nbody_batch_get_stats(b: int) -> nbody_stats:
     return s
 
 
-def nbody_batch_set_launch(b: int, force_grid: int = 0, target_items: int = 0) -> None:
-    _check(lib().nbody_batch_set_launch(C.c_void_p(b), int(force_grid), int(target_items)), "nbody_batch_set_launch")
+def nbody_batch_set_launch(b: int, force_grid: int = 0, target_items: int = 0, i_tile: int = 0) -> None:
+    _check(lib().nbody_batch_set_launch(C.c_void_p(b), int(force_grid), int(target_items), int(i_tile)),
+           "nbody_batch_set_launch")
+
+
+def nbody_batch_get_launch(b: int):
+    """(force_grid, target_items, i_tile) in use."""
+    out = (C.c_int32 * 3)()
+    _check(lib().nbody_batch_get_launch(C.c_void_p(b), out), "nbody_batch_get_launch")
+    return tuple(out)
+
+
+def nbody_batch_autotune(b: int, st: nbody_state, steps: int = 4) -> None:
+    _check(lib().nbody_batch_autotune(C.c_void_p(b), C.byref(st), int(steps)), "nbody_batch_autotune")

@@ -29,6 +29,7 @@ nbody_status check_config(const nbody_config *c)
     if (!(c->eps2 >= 0.0) || !std::isfinite(c->eps2)) return fail(NBODY_E_INVALID, "eps2 must be finite and >= 0");
     if (!(c->eta > 0.0) || !std::isfinite(c->eta)) return fail(NBODY_E_INVALID, "eta must be > 0");
     if (!(c->eta_start > 0.0) || !std::isfinite(c->eta_start)) return fail(NBODY_E_INVALID, "eta_start must be > 0");
+    if (c->dt_rule < 0 || c->dt_rule > 2) return fail(NBODY_E_INVALID, "dt_rule must be 0, 1 or 2 (got %d)", c->dt_rule);
     if (c->k_min < 0 || c->k_min > c->k_max || c->k_max > nb::kLevelMax)
         return fail(NBODY_E_INVALID, "need 0 <= k_min <= k_max <= 20 (got %d, %d)", c->k_min, c->k_max);
     return NBODY_OK;

@@ -7,7 +7,7 @@
 namespace nb {
 
 constexpr int kBatchMaxTarget = 64;   // largest items-per-cluster target the plan accepts
-constexpr int kBatchITile = 256;      // active rows per work item (= force workgroup size)
+constexpr int kBatchITileMax = 256;   // largest i-tile: active rows per work item (= force workgroup size)
 constexpr int kBatchSchedBlock = 1024;  // particles per scheduling block
 
 // Written by the plan kernel of every batched step and read by the kernels
@@ -58,6 +58,7 @@ struct BatchLaunch {
     int64_t n_hard;             // per cluster; every pair is unsoftened when eps2 == 0
     int force_grid;             // workgroups of the persistent force kernel
     int target_items;           // work items aimed for per cluster
+    int itile;                  // active rows per work item: 64 or 256
 };
 
 hipError_t batch_cid(const BatchLaunch &L, hipStream_t s);
@@ -70,7 +71,8 @@ hipError_t batch_force(const BatchLaunch &L, int order, int precision, const voi
 hipError_t batch_reduce(const BatchLaunch &L, int order, double *o0, double *o1, double *o2, double *o3,
                         hipStream_t s);
 hipError_t batch_correct(const BatchLaunch &L, const nbody_config &c, const nbody_state &st, hipStream_t s);
-// Workgroups of the persistent force kernel that fit on the device at once.
-int batch_force_resident(int order, int precision, int device);
+// Workgroups of the persistent force kernel (i-tile itile) that fit on the
+// device at once.
+int batch_force_resident(int order, int precision, int itile, int device);
 
 }  // namespace nb

@@ -30,8 +30,6 @@ namespace {
 
 constexpr int kBBlock = kBatchSchedBlock;
 constexpr int kBThreads = 256;  // threads per scheduling block (4 particles each)
-constexpr int kFBlock = kBatchITile;
-constexpr int kFTile = 128;     // j records per LDS tile
 
 __device__ __forceinline__ int64_t b_next(const int64_t *t_tick, const int32_t *level, int64_t i)
 {
@@ -136,7 +134,7 @@ __device__ void block_scan(int64_t *v, int n, int64_t *sh)
 __global__ void __launch_bounds__(kBThreads)
 k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
          const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int64_t *__restrict__ boff, BatchPlan *__restrict__ pl, int ncomp,
-         int target_items, BatchCounters *__restrict__ ctr)
+         int target_items, int itile, BatchCounters *__restrict__ ctr)
 {
     __shared__ int64_t sh[kBThreads];
     // per-cluster active counts and block offsets inside the cluster
@@ -156,7 +154,7 @@ k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restr
     for (int r = threadIdx.x; r < nc; r += kBThreads) {
         const int c = ord[r];
         const int64_t na = pl->nact[c], nn = off[c + 1] - off[c];
-        const int64_t tiles = (na + kFBlock - 1) / kFBlock;
+        const int64_t tiles = (na + itile - 1) / itile;
         int64_t sp = tiles > 0 ? (target_items + tiles - 1) / tiles : 0;
         const int64_t sp_max = nn / 512 > 1 ? nn / 512 : 1;
         sp = sp < 1 ? 1 : (sp > sp_max ? sp_max : sp);
@@ -261,15 +259,15 @@ k_b_predict(int64_t n, const int32_t *__restrict__ cid, const int64_t *__restric
 // Persistent force kernel.  Each workgroup takes items from the queue until
 // it is empty; item r (in cluster rank order) is (cluster ord[rank], i-tile,
 // j-split).  Every wave reaches the exit: the queue only grows.
-template <class Pol, int P>
-__global__ void __launch_bounds__(kFBlock)
+template <class Pol, int P, int BLOCK, int TILE>
+__global__ void __launch_bounds__(BLOCK)
 k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
           int nc, const int32_t *__restrict__ act, BatchPlan *__restrict__ pl, double eps2, int64_t n_hard,
           int ncomp, double *__restrict__ part)
 {
     using Rec = typename Pol::Rec;
     using ET = typename Pol::ET;
-    __shared__ Rec tile[2][kFTile];
+    __shared__ Rec tile[2][TILE];
     __shared__ int64_t s_item;
     const ET e2 = ET(eps2);
     const int64_t total = pl->ioff[nc];
@@ -295,7 +293,7 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
         const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
         const int64_t nh = n_hard < nn ? n_hard : nn;
         // this lane's active row
-        const int64_t q0 = tile_i * kFBlock + threadIdx.x;
+        const int64_t q0 = tile_i * BLOCK + threadIdx.x;
         const int64_t q = q0 < na ? q0 : na - 1;
         const int32_t *al = act + pl->aoff[c];
         typename Pol::I ip[1];
@@ -310,7 +308,7 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
         }
         hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
         const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
-        lds_tiles<Pol, 1, kFBlock, 2, kFTile>(rec, js0, j1, e2, ip, tile, acc);
+        lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, tile, acc);
         if (q0 < na) {
             double *dst = part + pl->poff[c] + split * ncomp * na;
 #pragma unroll
@@ -353,7 +351,7 @@ k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *_
             const int64_t *__restrict__ tnext, const BatchPlan *__restrict__ pl, double *__restrict__ x,
             double *__restrict__ v, double *__restrict__ d0, double *__restrict__ d1, double *__restrict__ d2,
             double *__restrict__ d3, double *__restrict__ d4, double *__restrict__ d5, int64_t *__restrict__ t_tick,
-            int32_t *__restrict__ level, const double *__restrict__ force, double eta, int k_min, int k_max,
+            int32_t *__restrict__ level, const double *__restrict__ force, double eta, int rule, int k_min, int k_max,
             BatchCounters *__restrict__ ctr)
 {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -362,7 +360,7 @@ k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *_
     if (i < 0 || i >= n) return;
     double *dst[6] = {d0, d1, d2, d3, d4, d5};
     const double *fnew[4] = {force, force + 3 * n, force + 6 * n, force + 9 * n};
-    const int fl = correct_one<P>(n, i, tnext[cid[i]], fnew, n, r, x, v, dst, t_tick, level, eta, k_min, k_max);
+    const int fl = correct_one<P>(n, i, tnext[cid[i]], fnew, n, r, x, v, dst, t_tick, level, eta, rule, k_min, k_max);
     if (fl & 2) atomicAdd(&ctr->underflow, 1ull);
     if (fl & 1) atomicAdd(&ctr->nonfinite, 1ull);
 }
@@ -377,9 +375,14 @@ unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 template <class Pol, int P>
 hipError_t force_p(const BatchLaunch &L, const void *rec, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_b_force<Pol, P>), dim3(L.force_grid), dim3(kFBlock), 0, s,
-                       static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
-                       L.n_hard, 3 * (P / 2), L.part);
+    if (L.itile == 64)
+        hipLaunchKernelGGL((k_b_force<Pol, P, 64, 64>), dim3(L.force_grid), dim3(64), 0, s,
+                           static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
+                           L.n_hard, 3 * (P / 2), L.part);
+    else
+        hipLaunchKernelGGL((k_b_force<Pol, P, 256, 128>), dim3(L.force_grid), dim3(256), 0, s,
+                           static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
+                           L.n_hard, 3 * (P / 2), L.part);
     return hipGetLastError();
 }
 
@@ -408,27 +411,30 @@ hipError_t batch_requeue(const BatchLaunch &L, hipStream_t s)
 }
 
 template <class Pol, int P>
-int resident_p(int device)
+int resident_p(int itile, int device)
 {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P>, kFBlock, 0) != hipSuccess) return 0;
+    const hipError_t e = itile == 64
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 64, 64>, 64, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 256, 128>, 256, 0);
+    if (e != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     return per_cu * cus;
 }
 
 template <int P>
-int resident_prec(int precision, int device)
+int resident_prec(int precision, int itile, int device)
 {
-    if (precision == NBODY_MIXED) return resident_p<PolMx<P, false>, P>(device);
-    if (precision == NBODY_DS) return resident_p<PolDS<P, false>, P>(device);
-    return resident_p<PolF64<P, false>, P>(device);
+    if (precision == NBODY_MIXED) return resident_p<PolMx<P, false>, P>(itile, device);
+    if (precision == NBODY_DS) return resident_p<PolDS<P, false>, P>(itile, device);
+    return resident_p<PolF64<P, false>, P>(itile, device);
 }
 
-int batch_force_resident(int order, int precision, int device)
+int batch_force_resident(int order, int precision, int itile, int device)
 {
-    if (order == 4) return resident_prec<4>(precision, device);
-    if (order == 6) return resident_prec<6>(precision, device);
-    return resident_prec<8>(precision, device);
+    if (order == 4) return resident_prec<4>(precision, itile, device);
+    if (order == 6) return resident_prec<6>(precision, itile, device);
+    return resident_prec<8>(precision, itile, device);
 }
 
 hipError_t batch_cid(const BatchLaunch &L, hipStream_t s)
@@ -444,7 +450,7 @@ hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_a
     hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, all_active,
                        L.plan, L.tnext, L.bcnt);
     hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.nb, L.off, L.ord, L.tnext, L.bcnt, L.boff,
-                       L.plan, 3 * (order / 2), L.target_items, L.ctr);
+                       L.plan, 3 * (order / 2), L.target_items, L.itile, L.ctr);
     hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.boff,
                        all_active, L.plan, L.act);
     return hipGetLastError();
@@ -489,7 +495,7 @@ hipError_t batch_correct(const BatchLaunch &L, const nbody_config &c, const nbod
 #define NB_BC(P)                                                                                              \
     hipLaunchKernelGGL((k_b_correct<P>), dim3(g), dim3(256), 0, s, L.n, L.nc, L.act, L.cid, L.tnext, L.plan,     \
                        st.x, st.v, st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, st.level,    \
-                       L.force, c.eta, int(c.k_min), int(c.k_max), L.ctr)
+                       L.force, c.eta, dt_rule_of(c), int(c.k_min), int(c.k_max), L.ctr)
     if (c.order == 4) NB_BC(4);
     else if (c.order == 6) NB_BC(6);
     else NB_BC(8);

@@ -62,10 +62,10 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.tcur = take(nc * sizeof(int64_t));
     L.ctr = take(sizeof(nb::BatchCounters));
     L.act = take(n * sizeof(int32_t));
-    // split partials: a cluster with a active rows in t tiles of 256 takes
-    // s <= max(1, ceil(T / t)) splits, so s * a <= T * 256 + a; 12 components
+    // split partials: a cluster with a active rows in t i-tiles of I rows
+    // takes s <= max(1, ceil(T / t)) splits, so s * a <= T * I + a; 12 components
     // (the order-8 initialisation passes)
-    L.part = take(12 * (nc * size_t(nb::kBatchMaxTarget) * nb::kBatchITile + n) * sizeof(double));
+    L.part = take(12 * (nc * size_t(nb::kBatchMaxTarget) * nb::kBatchITileMax + n) * sizeof(double));
     L.force = take(12 * n * sizeof(double));
     L.rec = take(n * size_t(std::max(nb::record_bytes(c.order, c.precision), nb::record_bytes(8, NBODY_FP64))));
     L.energy = take(2 * size_t(sum_energy_blocks(off)) * sizeof(double));
@@ -229,6 +229,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.eps2 = cfg->eps2;
     L.n_hard = cfg->eps2 == 0.0 ? (int64_t(1) << 40) : cfg->n_hard;
     L.target_items = 16;
+    L.itile = 64;
     nb::BatchPlan hp{};
     hp.queue = 0;
     hp.t_end = INT64_MAX;
@@ -243,7 +244,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) {
         b->force_grid_req = 0;
-        L.force_grid = nb::batch_force_resident(cfg->order, cfg->precision, b->device);
+        L.force_grid = nb::batch_force_resident(cfg->order, cfg->precision, L.itile, b->device);
         if (L.force_grid <= 0) e = hipErrorInvalidDeviceFunction;
     }
     if (e == hipSuccess) e = hipMemcpyAsync(L.plan, &hp, sizeof(hp), hipMemcpyHostToDevice, b->stream);
@@ -446,16 +447,79 @@ nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out)
     return NBODY_OK;
 }
 
-nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items)
+nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items, int32_t i_tile)
 {
     if (!b) return fail(NBODY_E_INVALID, "batch is NULL");
     if (force_grid < 0 || force_grid > (1 << 20)) return fail(NBODY_E_INVALID, "force_grid must be in [0, 2^20]");
     if (target_items < 0 || target_items > nb::kBatchMaxTarget)
         return fail(NBODY_E_INVALID, "target_items must be in [0, %d]", nb::kBatchMaxTarget);
+    if (i_tile != 0 && i_tile != 64 && i_tile != 256) return fail(NBODY_E_INVALID, "i_tile must be 0, 64 or 256");
+    nb::BatchLaunch &L = b->L;
+    L.itile = i_tile > 0 ? i_tile : 64;
+    L.target_items = target_items > 0 ? target_items : 16;
     b->force_grid_req = force_grid;
-    b->L.force_grid = force_grid > 0 ? force_grid : nb::batch_force_resident(b->cfg.order, b->cfg.precision, b->device);
-    b->L.target_items = target_items > 0 ? target_items : 16;
+    L.force_grid = force_grid > 0 ? force_grid : nb::batch_force_resident(b->cfg.order, b->cfg.precision, L.itile, b->device);
+    if (L.force_grid <= 0) return fail(NBODY_E_HIP, "occupancy query of the batched force kernel failed");
     return NBODY_OK;
+}
+
+nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3])
+{
+    if (!b || !out) return fail(NBODY_E_INVALID, "batch and out are required");
+    out[0] = b->L.force_grid;
+    out[1] = b->L.target_items;
+    out[2] = b->L.itile;
+    return NBODY_OK;
+}
+
+nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *st, int32_t steps)
+{
+    if (!b) return fail(NBODY_E_INVALID, "batch is NULL");
+    nbody_status s = check_bstate(b, st);
+    if (s != NBODY_OK) return s;
+    if (steps < 1 || steps > 100000) return fail(NBODY_E_INVALID, "steps must be in [1, 100000]");
+    drop_graph(b);
+    hipEvent_t e0, e1;
+    NB_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(NBODY_E_HIP, "hipEventCreate failed");
+    }
+    const int itiles[2] = {64, 256};
+    const int targets[5] = {4, 8, 16, 32, 64};
+    double best = -1.0;
+    int best_i = 64, best_t = 16;
+    nb::BatchCounters c0, c1;
+    for (int it : itiles)
+        for (int tg : targets) {
+            s = nbody_batch_set_launch(b, b->force_grid_req, tg, it);
+            // one untimed step, then `steps` timed ones
+            if (s == NBODY_OK) s = enqueue_step(b, *st);
+            if (s == NBODY_OK && hipMemcpyAsync(&c0, b->L.ctr, sizeof(c0), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+                s = fail(NBODY_E_HIP, "counter copy failed");
+            if (s == NBODY_OK && hipEventRecord(e0, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
+            for (int r = 0; s == NBODY_OK && r < steps; ++r) s = enqueue_step(b, *st);
+            if (s == NBODY_OK && hipEventRecord(e1, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
+            if (s == NBODY_OK && hipMemcpyAsync(&c1, b->L.ctr, sizeof(c1), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+                s = fail(NBODY_E_HIP, "counter copy failed");
+            if (s == NBODY_OK) s = sync(b);
+            float ms = 0.0f;
+            if (s == NBODY_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(NBODY_E_HIP, "event timing failed");
+            if (s != NBODY_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return s;
+            }
+            const double rate = double(c1.interactions - c0.interactions) / std::max(double(ms), 1e-6);
+            if (rate > best) {
+                best = rate;
+                best_i = it;
+                best_t = tg;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return nbody_batch_set_launch(b, b->force_grid_req, best_t, best_i);
 }
 
 }  // extern "C"

@@ -9,7 +9,8 @@
 // time-symmetric Hermite corrector (order 4: Hut & Makino; orders 6 and 8:
 // Nitadori & Makino 2008), derivatives at the end of the step from the
 // Hermite interpolant through both ends, Aarseth's step criterion (order 4)
-// and its generalisation (orders 6 and 8, Nitadori & Makino 2008).
+// and its generalisation (orders 6 and 8, Nitadori & Makino 2008), of the
+// scheme's order or of order 4.
 #pragma once
 
 #include "internal.h"
@@ -125,14 +126,15 @@ __device__ __forceinline__ double interp(int m, const double *Ps, const double *
 
 // Corrector + interpolation + new step of particle i, whose step ends at t1.
 // fnew[k][stride * c + row] are the force derivatives a^(k) at t1 (k < p/2).
-// Returns flags: bit 0 = a corrected value is not finite, bit 1 = dt_crit fell
-// below 2^-k_max.
+// rule (orders 6, 8): 1 = generalised criterion of order P, 2 = its order-4
+// form, which reads only a .. a^(3).  Returns flags: bit 0 = a corrected
+// value is not finite, bit 1 = dt_crit fell below 2^-k_max.
 template <int P>
 __device__ __forceinline__ int correct_one(int64_t n, int64_t i, int64_t t1, const double *const *fnew,
                                            int64_t stride, int64_t row, double *__restrict__ x,
                                            double *__restrict__ v, double *const *dst,
                                            int64_t *__restrict__ t_tick, int32_t *__restrict__ level, double eta,
-                                           int k_min, int k_max)
+                                           int rule, int k_min, int k_max)
 {
     constexpr int q = P / 2;
     const double h = double(t1 - t_tick[i]) * (1.0 / double(kTicksPerUnit));
@@ -204,9 +206,14 @@ __device__ __forceinline__ int correct_one(int64_t n, int64_t i, int64_t t1, con
     if constexpr (P == 4) {
         dtc = __builtin_sqrt(eta * __builtin_fma(F[0], F[2], F[1] * F[1]) / __builtin_fma(F[1], F[3], F[2] * F[2]));
     } else {
+        // eta (A_1 / A_(q-2))^(1/(q-3)), A_k = sqrt(|a^(k-1)| |a^(k+1)|) + |a^(k)|, q = P or 4
         const double a1 = __builtin_sqrt(F[0] * F[2]) + F[1];
-        const double ak = __builtin_sqrt(F[P - 3] * F[P - 1]) + F[P - 2];
-        dtc = (P == 6) ? eta * cbrt(a1 / ak) : eta * pow(a1 / ak, 0.2);
+        if (rule == 2) {
+            dtc = eta * (a1 / (__builtin_sqrt(F[1] * F[3]) + F[2]));
+        } else {
+            const double ak = __builtin_sqrt(F[P - 3] * F[P - 1]) + F[P - 2];
+            dtc = (P == 6) ? eta * cbrt(a1 / ak) : eta * pow(a1 / ak, 0.2);
+        }
     }
     const int old = level[i];
     int k = level_for(dtc, k_min, k_max);

@@ -82,7 +82,7 @@ k_correct(int64_t n, int64_t n_act_host, const int32_t *__restrict__ act, const 
           double *__restrict__ d1, double *__restrict__ d2, double *__restrict__ d3, double *__restrict__ d4,
           double *__restrict__ d5, int64_t *__restrict__ t_tick, int32_t *__restrict__ level,
           const double *__restrict__ f0, const double *__restrict__ f1, const double *__restrict__ f2,
-          const double *__restrict__ f3, double eta, int k_min, int k_max, DevScalars *sc)
+          const double *__restrict__ f3, double eta, int rule, int k_min, int k_max, DevScalars *sc)
 {
     // active count and end time from the host, or from the device scheduler
     const int64_t qi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -93,7 +93,7 @@ k_correct(int64_t n, int64_t n_act_host, const int32_t *__restrict__ act, const 
     if (i < 0 || i >= n) return;   // an index outside [0, n) is ignored
     double *dst[6] = {d0, d1, d2, d3, d4, d5};
     const double *fnew[4] = {f0, f1, f2, f3};
-    const int fl = correct_one<P>(n, i, t1, fnew, na, qi, x, v, dst, t_tick, level, eta, k_min, k_max);
+    const int fl = correct_one<P>(n, i, t1, fnew, na, qi, x, v, dst, t_tick, level, eta, rule, k_min, k_max);
     if (fl & 2) atomicAdd(&sc->underflow, 1ull);
     if (fl & 1) atomicAdd(&sc->nonfinite, 1ull);
 }
@@ -355,7 +355,7 @@ hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t 
 #define NB_CORR(P)                                                                                             \
     hipLaunchKernelGGL((k_correct<P>), dim3(g), dim3(256), 0, s, c.n, n_act, act, src, t_tick_host,            \
                        st.x, st.v, st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, st.level, \
-                       f[0], f[1], f[2], f[3], c.eta, int(c.k_min), int(c.k_max), sc)
+                       f[0], f[1], f[2], f[3], c.eta, dt_rule_of(c), int(c.k_min), int(c.k_max), sc)
     if (c.order == 4) NB_CORR(4);
     else if (c.order == 6) NB_CORR(6);
     else NB_CORR(8);

@@ -32,6 +32,17 @@ constexpr int kMixedChunk = 128;            // FP32 partial-sum length in MIXED 
 constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act_pad * n_split)
 constexpr int kMaxComp = 13;                // acc3 + jerk3 + snap3 + crackle3 + pot
 
+// Time-step rule in use (orders 6, 8): 1 = generalised criterion of the
+// scheme's order, 2 = its order-4 form.  dt_rule 0 picks the order-4 form
+// where the interpolated derivatives of the full-order criterion are
+// dominated by rounding noise at short steps: a force with single-precision
+// arithmetic, or order 8.
+inline int dt_rule_of(const nbody_config &c)
+{
+    if (c.dt_rule != 0) return c.dt_rule;
+    return (c.precision != NBODY_FP64 || c.order == 8) ? 2 : 1;
+}
+
 // Components of a force result for a Hermite order: 3 per derivative + pot.
 inline int n_comp(int order) { return 3 * (order / 2) + 1; }
 

@@ -26,7 +26,7 @@ class Simulation:
 
     def __init__(self, m, x, v, order: int = 4, precision: str | int = "fp64", eps2: float = 1e-8,
                  n_hard: int = 0, eta: float = 0.01, eta_start: float = 0.01, k_min: int = 3, k_max: int = 20,
-                 device: str = "cuda:0", stream: torch.cuda.Stream | None = None):
+                 device: str = "cuda:0", stream: torch.cuda.Stream | None = None, dt_rule: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the N-body library runs only on the device")
         self.device = torch.device(device)
@@ -34,8 +34,9 @@ class Simulation:
         prec = abi.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         n = int(np.asarray(m).shape[0])
         self.n = n
+        self.dt_rule = abi.effective_dt_rule(self.order, prec, dt_rule)
         self.cfg = abi.nbody_config(self.order, prec, n, int(n_hard), float(eps2), float(eta), float(eta_start),
-                                    int(k_min), int(k_max))
+                                    int(k_min), int(k_max), int(dt_rule))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.m = _dev(m, torch.float64, self.device)
         self.x = _dev(np.asarray(x).reshape(3, n), torch.float64, self.device)
@@ -160,7 +161,7 @@ class Batch:
 
     def __init__(self, clusters, order: int = 6, precision: str | int = "mixed", eps2: float = 1e-8,
                  n_hard: int = 0, eta: float = 0.1, eta_start: float = 0.01, k_min: int = 3, k_max: int = 20,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", dt_rule: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the N-body library runs only on the device")
         self.device = torch.device(device)
@@ -171,8 +172,9 @@ class Batch:
         self.nc = len(sizes)
         n = self.off[-1]
         self.n = n
+        self.dt_rule = abi.effective_dt_rule(self.order, prec, dt_rule)
         self.cfg = abi.nbody_config(self.order, prec, n, int(n_hard), float(eps2), float(eta), float(eta_start),
-                                    int(k_min), int(k_max))
+                                    int(k_min), int(k_max), int(dt_rule))
         self.stream = torch.cuda.Stream(self.device)
         m = np.concatenate([np.asarray(c[0], dtype=np.float64) for c in clusters])
         x = np.concatenate([np.asarray(c[1], dtype=np.float64).reshape(3, -1) for c in clusters], axis=1)
@@ -204,8 +206,14 @@ class Batch:
         except Exception:
             pass
 
-    def set_launch(self, force_grid: int = 0, target_items: int = 0):
-        abi.nbody_batch_set_launch(self.b, force_grid, target_items)
+    def set_launch(self, force_grid: int = 0, target_items: int = 0, i_tile: int = 0):
+        abi.nbody_batch_set_launch(self.b, force_grid, target_items, i_tile)
+
+    def get_launch(self):
+        return abi.nbody_batch_get_launch(self.b)
+
+    def autotune(self, steps: int = 4):
+        abi.nbody_batch_autotune(self.b, self.state, steps)
 
     def set_end(self, t_end_tick: int):
         abi.nbody_batch_set_end(self.b, t_end_tick)
@@ -248,6 +256,17 @@ class Batch:
         return {"m": self.m.cpu().numpy(), "x": self.x.cpu().numpy(), "v": self.v.cpu().numpy(),
                 "d": [t.cpu().numpy() for t in self.d], "t_tick": self.t_tick.cpu().numpy(),
                 "level": self.level.cpu().numpy()}
+
+    def load_state(self, h: dict):
+        """Overwrite the device state from a to_numpy()-style dict of host arrays."""
+        self.stream.synchronize()
+        self.x.copy_(_dev(h["x"], torch.float64, self.device))
+        self.v.copy_(_dev(h["v"], torch.float64, self.device))
+        for k, a in enumerate(h["d"]):
+            self.d[k].copy_(_dev(a, torch.float64, self.device))
+        self.t_tick.copy_(_dev(h["t_tick"], torch.int64, self.device))
+        self.level.copy_(_dev(h["level"], torch.int32, self.device))
+        torch.cuda.synchronize(self.device)
 
     def cluster(self, h: dict, c: int) -> dict:
         """Cluster c's slice of a to_numpy() dict."""

@@ -85,13 +85,13 @@ def oracle_correct(ocfg, os0, act, T, F):
         for k in range(p - 2):
             d[k][:, i] = Dall[k]
         dnorm[:, r] = np.linalg.norm(Dall, axis=1)
-        dtc = oracle.dt_crit(p, ocfg.eta, dnorm[:, r])
+        dtc = oracle.dt_crit(p, ocfg.eta, dnorm[:, r], ocfg.dt_rule)
         lv[i] = oracle.new_level(dtc, int(os0.level[i]), T, ocfg.k_min, ocfg.k_max)
         margin[r] = abs(np.log2(dtc) - np.round(np.log2(dtc)))
     return x, v, d, lv, scale, margin, dnorm
 
 
-def compare_corrected(got, want, act, order, rel_force_err, tag):
+def compare_corrected(got, want, act, order, rel_force_err, tag, rule=1):
     """x, v to FP64 rounding; interpolated derivatives within their rounding
     scale (amplified by the force difference); levels equal except where
     log2(dt_crit) lies within its own rounding uncertainty of an integer
@@ -100,11 +100,16 @@ def compare_corrected(got, want, act, order, rel_force_err, tag):
     q = order // 2
     # relative uncertainty of each interpolated |a^(k)| from its rounding
     # scale, carried into log2(dt_crit): the criterion uses a^(p-3..p-1)
-    # (order 4: a^(2), a^(3)) under a 1/(p-3) power (order 4: a square root)
+    # under a 1/(p-3) power (order 4: a^(2), a^(3) under a square root; the
+    # order-4 form at orders 6, 8: a^(1..3), power 1)
     unc = (512 * 2.0 ** -53 + rel_force_err) * np.linalg.norm(scale, axis=1) / np.maximum(dnorm[q:], 1e-300)
-    ks = [2, 3] if order == 4 else list(range(order - 3, order))
-    root = 2.0 if order == 4 else float(order - 3)
-    margin_tol = 4.0 * sum(unc[k - q] for k in ks if k >= q) / root / np.log(2.0) + 1e-12
+    if order == 4:
+        ks, root = [2, 3], 2.0
+    elif rule == 2:
+        ks, root = [1, 2, 3], 1.0
+    else:
+        ks, root = list(range(order - 3, order)), float(order - 3)
+    margin_tol = 4.0 * sum((unc[k - q] for k in ks if k >= q), np.zeros(act.size)) / root / np.log(2.0) + 1e-12
     for name, g, w in [("x", got["x"], x), ("v", got["v"], v)]:
         st = err_stats(rel_err(g[:, act], w[:, act]))
         say("%s order %d %s rms %.2e max %.2e" % (tag, order, name, st["rms"], st["max"]))

@@ -27,10 +27,10 @@ def test_library_exports_every_declared_symbol():
 
 def _cfg(**kw):
     base = dict(order=6, precision=abi.NBODY_MIXED, n=1000, n_hard=0, eps2=1e-8, eta=0.1, eta_start=0.01,
-                k_min=3, k_max=20)
+                k_min=3, k_max=20, dt_rule=0)
     base.update(kw)
     return abi.nbody_config(base["order"], base["precision"], base["n"], base["n_hard"], base["eps2"],
-                            base["eta"], base["eta_start"], base["k_min"], base["k_max"])
+                            base["eta"], base["eta_start"], base["k_min"], base["k_max"], base["dt_rule"])
 
 
 def test_workspace_size_scales_with_n():
@@ -43,7 +43,7 @@ def test_workspace_size_scales_with_n():
 
 @pytest.mark.parametrize("kw", [dict(order=5), dict(order=10), dict(precision=3), dict(n=1), dict(n_hard=2000),
                                 dict(eps2=-1.0), dict(eta=0.0), dict(eta_start=-1.0), dict(k_min=5, k_max=4),
-                                dict(k_max=21), dict(eps2=float("nan"))])
+                                dict(k_max=21), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1)])
 def test_config_validation(kw):
     with pytest.raises(abi.NBodyError) as e:
         abi.nbody_workspace_size(_cfg(**kw))
@@ -109,5 +109,6 @@ def test_batch_null_handles_are_rejected():
     assert L.nbody_batch_destroy(None) == abi.NBODY_E_INVALID
     assert L.nbody_batch_step(None, None, 1) == abi.NBODY_E_INVALID
     assert L.nbody_batch_replay(None, 1) == abi.NBODY_E_INVALID
-    assert L.nbody_batch_set_launch(None, 0, 0) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_set_launch(None, 0, 0, 0) == abi.NBODY_E_INVALID
+    assert L.nbody_batch_autotune(None, None, 1) == abi.NBODY_E_INVALID
     assert L.nbody_batch_poll(None, None, None) == abi.NBODY_E_INVALID

@@ -43,7 +43,7 @@ def _batch(models, order, precision="fp64", eps2=1e-8, n_hard=2, eta=None, k_min
 def _ocfg(B):
     c = B.cfg
     return OracleConfig(order=c.order, eps2=c.eps2, n_hard=c.n_hard, eta=c.eta, eta_start=c.eta_start,
-                        k_min=c.k_min, k_max=c.k_max)
+                        k_min=c.k_min, k_max=c.k_max, dt_rule=B.dt_rule)
 
 
 def _ostate(hc, order):
@@ -126,12 +126,16 @@ def test_batch_force_all_active(order, precision):
             assert st["rms"] <= LOW_TOL[key], (key, st)
 
 
+@pytest.mark.parametrize("shape", [(64, 16), (256, 16), (64, 64), (256, 4), (64, 1)])
 @pytest.mark.parametrize("order", [4, 6, 8])
-def test_batch_force_block_steps(order):
+def test_batch_force_block_steps(order, shape):
     """Individual block steps: every cluster at its own time with its own
-    (small) active set, j-ranges split to fill the work queue."""
+    (small) active set, j-ranges split to fill the work queue; i-tiles of 64
+    and 256 rows, 1 to 64 work items aimed for per cluster."""
     models = _clusters(920)
     B = _batch(models, order, "fp64")
+    B.set_launch(0, shape[1], shape[0])
+    assert B.get_launch()[1:] == (shape[1], shape[0])
     B.init()
     ocfg = _ocfg(B)
     errs = {k: [] for k in KEYS}
@@ -175,7 +179,7 @@ def test_batch_step_parity(order, precision):
             assert np.all(got["t_tick"][rest] == hc["t_tick"][rest])
             want = oracle_correct(ocfg, os0, act, T, F)
             if precision == "fp64":
-                compare_corrected(got, want, act, order, rel_force, "batch step c%d" % c)
+                compare_corrected(got, want, act, order, rel_force, "batch step c%d" % c, B.dt_rule)
             else:
                 st = err_stats(rel_err(got["v"][:, act] - os0.v[:, act], want[1][:, act] - os0.v[:, act]))
                 assert st["rms"] <= 2e-5, (step, c, st)
@@ -272,3 +276,27 @@ def test_batch_unsoftened_pairs():
         for k in range(4):
             st = err_stats(rel_err(hc["d"][k], os_.d[k]))
             assert st["max"] <= 1e-9, (c, k, st)
+
+
+def test_batch_autotune_keeps_parity():
+    """The autotuner advances the clusters by real steps and leaves a valid
+    shape; the next steps still match the oracle."""
+    models = _clusters(980)
+    B = _batch(models, 6, "mixed")
+    B.init()
+    B.autotune(1)
+    grid, target, itile = B.get_launch()
+    say("autotuned batch shape: grid %d target %d i_tile %d" % (grid, target, itile))
+    assert grid > 0 and target in (4, 8, 16, 32, 64) and itile in (64, 256)
+    assert B.stats().steps == 20
+    ocfg = _ocfg(B)
+    errs = {k: [] for k in KEYS}
+    for step in range(3):
+        h0 = B.to_numpy()
+        B.step(1)
+        aoff, act, f = B.last_step()
+        _force_errors(B, models, h0, aoff, act.cpu().numpy(), f.cpu().numpy(), ocfg, 6, errs)
+    for key in KEYS[:3]:
+        st = err_stats(np.concatenate(errs[key]))
+        say("after autotune %s rms %.2e max %.2e" % (key, st["rms"], st["max"]))
+        assert st["max"] <= 50 * LOW_TOL[key]

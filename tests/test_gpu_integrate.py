@@ -29,7 +29,7 @@ def _sim(model, order, precision="fp64", eps2=1e-8, n_hard=0, eta=None, k_min=3,
 def _ocfg(sim):
     c = sim.cfg
     return OracleConfig(order=c.order, eps2=c.eps2, n_hard=c.n_hard, eta=c.eta, eta_start=c.eta_start,
-                        k_min=c.k_min, k_max=c.k_max)
+                        k_min=c.k_min, k_max=c.k_max, dt_rule=sim.dt_rule)
 
 
 def _ostate(h, order):
@@ -133,7 +133,7 @@ def test_correct_parity(order):
     sim.correct(torch.as_tensor(act, device=dev), T, f)
     got = sim.to_numpy()
     assert np.all(got["t_tick"][act] == T)
-    compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, 0.0, "correct")
+    compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, 0.0, "correct", sim.dt_rule)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -160,7 +160,7 @@ def test_step_parity(order, precision):
         got = sim.to_numpy()
         assert np.all(got["t_tick"][act] == T)
         if precision == "fp64":
-            compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, rel_force, "step")
+            compare_corrected(got, oracle_correct(ocfg, os0, act, T, F), act, order, rel_force, "step", sim.dt_rule)
         else:
             # MIXED: the corrected state differs by the force error times h
             want = oracle_correct(ocfg, os0, act, T, F)
@@ -206,28 +206,36 @@ def test_c1_integration_vs_oracle():
     assert dx["rms"] < 1e-8
 
 
-def test_mixed_energy_drift_matches_fp64():
-    """6th order, Plummer n=4096, eta=0.1, to t = 1/4: the MIXED force keeps
-    |dE/E| within twice the oracle's drift."""
-    model = nbody_ics.plummer(4096, 12)
-    drift = {}
+@pytest.mark.parametrize("order", [6, 8])
+def test_mixed_energy_drift_matches_oracle(order):
+    """Plummer n=8192, eta=0.1, to t = 1/8 with the default time-step rule of
+    each precision: |dE/E| of the MIXED force within twice the oracle's drift
+    under the same rule; no particle stuck at the smallest step; FP64 (its own
+    rule) against the oracle likewise."""
+    model = nbody_ics.plummer(8192, 12)
+    t_end = TICKS // 8
     for prec in ("mixed", "fp64"):
-        sim = _sim(model, 6, precision=prec, eta=0.1)
+        sim = _sim(model, order, precision=prec, eta=0.1)
         sim.init()
         E0 = sum(sim.energy())
-        sim.integrate(TICKS // 4)
+        steps = sim.integrate(t_end)
         E1 = sum(sim.energy())
-        drift[prec] = abs((E1 - E0) / E0)
-    ocfg = OracleConfig(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
-    os_ = oracle.State(model.m, model.x, model.v, 6)
-    oracle.init(ocfg, os_)
-    Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
-    oracle.integrate(ocfg, os_, TICKS // 4)
-    Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
-    do = abs((Eo1 - Eo0) / Eo0)
-    say("drift mixed %.3e fp64 %.3e oracle %.3e" % (drift["mixed"], drift["fp64"], do))
-    assert drift["fp64"] <= 2.0 * do + 1e-13
-    assert drift["mixed"] <= 2.0 * do + 1e-10
+        dg = abs((E1 - E0) / E0)
+        got = sim.to_numpy()
+        ocfg = _ocfg(sim)
+        os_ = oracle.State(model.m, model.x, model.v, order)
+        oracle.init(ocfg, os_)
+        Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+        st = oracle.integrate(ocfg, os_, t_end)
+        Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+        do = abs((Eo1 - Eo0) / Eo0)
+        say("order %d %s (rule %d): %d steps (oracle %d), |dE/E| %.3e (oracle %.3e), level-20 particles %d, "
+            "dt underflows %d" % (order, prec, sim.dt_rule, steps, st["steps"], dg, do,
+                                  int(np.sum(got["level"] == 20)), sim.stats().dt_underflow))
+        assert np.all(got["t_tick"] == t_end)
+        assert sim.stats().dt_underflow == 0
+        assert steps <= 1.5 * st["steps"]
+        assert dg <= 2.0 * do + (1e-13 if prec == "fp64" else 1e-10)
 
 
 def test_nonfinite_is_reported():

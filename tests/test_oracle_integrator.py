@@ -146,6 +146,27 @@ def test_dt_crit_circular_orbit(oracle_lib, p):
     assert abs(oracle.dt_crit(p, eta, F) - want) < 1e-14 * want
 
 
+@pytest.mark.parametrize("p", [6, 8])
+def test_dt_crit_order4_form(oracle_lib, p):
+    """The order-4 form of the generalised criterion: eta/omega on a circular
+    orbit like the full-order one, reads only a .. a^(3) (any value of the
+    higher derivatives, even NaN, leaves it unchanged) and so does not
+    depend on the scheme's order; a^(3) does change it."""
+    w = 1.7
+    F = np.array([2.3 * w ** k for k in range(p)])
+    eta = 0.1
+    assert abs(oracle.dt_crit(p, eta, F, rule=2) - eta / w) < 1e-14 * eta / w
+    G = F.copy()
+    G[4:] = [np.nan, 1e30, 0.0, 7.0][: p - 4]
+    assert oracle.dt_crit(p, eta, G, rule=2) == oracle.dt_crit(p, eta, F, rule=2)
+    assert oracle.dt_crit(p, eta, F, rule=2) == oracle.dt_crit(6, eta, F[:6], rule=2)
+    H = F.copy()
+    H[3] *= 4.0
+    assert oracle.dt_crit(p, eta, H, rule=2) < oracle.dt_crit(p, eta, F, rule=2)
+    # the full-order criterion does read the higher derivatives
+    assert oracle.dt_crit(p, eta, G * np.r_[1, 1, 1, 1, [2.0] * (p - 4)], rule=1) != oracle.dt_crit(p, eta, F, rule=1)
+
+
 def test_dt_crit_aarseth_mixed_magnitudes(oracle_lib):
     F = np.array([1.0, 2.0, 4.0, 16.0])
     # sqrt(eta (1*4 + 2^2) / (2*16 + 4^2)) = sqrt(eta / 6)
