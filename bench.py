@@ -182,8 +182,8 @@ def run_batched(args):
     kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
     clusters = [(m.m, m.x, m.v) for m in models]
     B = Batch(clusters, precision="mixed", **kw)
-    if args.batch_target or args.batch_grid or args.batch_itile:
-        B.set_launch(args.batch_grid, args.batch_target, args.batch_itile)
+    if args.batch_per_wg or args.batch_grid or args.batch_itile:
+        B.set_launch(args.batch_grid, args.batch_per_wg, args.batch_itile)
     t0 = time.perf_counter()
     B.init()
     B.synchronize()
@@ -209,7 +209,7 @@ def run_batched(args):
         t0 = time.perf_counter()
         B.autotune(args.autotune_steps)
         tuned = B.get_launch()
-        log("[batched] autotune (%d steps per shape): force_grid %d, target_items %d, i_tile %d, %.1f s"
+        log("[batched] autotune (%d steps per shape): force_grid %d, items per workgroup %d, i_tile %d, %.1f s"
             % (args.autotune_steps, tuned[0], tuned[1], tuned[2], time.perf_counter() - t0))
     shape = B.get_launch()
     h = B.to_numpy()   # the common starting state of the three timed runs
@@ -230,7 +230,7 @@ def run_batched(args):
                                       min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20))
     batched = {"interactions_per_s": inter / wall, "ms_per_batched_step": wall / args.steps * 1e3,
                "interactions": inter, "mean_active_per_batched_step": nact,
-               "launch": {"force_grid": shape[0], "target_items": shape[1], "i_tile": shape[2]},
+               "launch": {"force_grid": shape[0], "items_per_wg": shape[1], "i_tile": shape[2]},
                "cluster_time_range": [min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20]}
     del B
     # the same steps launched eagerly (no graph)
@@ -251,8 +251,8 @@ def run_batched(args):
              "ms_per_batched_step": ewall / args.steps * 1e3}
     del E
     # one context per cluster, the same number of block steps each, same start
-    tot_inter, tot_wall, tot_steps = 0.0, 0.0, 0
-    for c, m in enumerate(models):
+    tot_inter, tot_wall, tot_steps = 0.0, 1e-30, 0
+    for c, m in enumerate([] if args.skip_per_cluster else models):
         sim = Simulation(m.m, m.x, m.v, precision="mixed", **kw)
         a, b = sum(sizes[:c]), sum(sizes[:c + 1])
         sim.load_state(h["x"][:, a:b], h["v"][:, a:b], [d[:, a:b] for d in h["d"]], h["t_tick"][a:b],
@@ -306,11 +306,12 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--workload", choices=["king1m", "batched"], default="king1m")
     ap.add_argument("--clusters", type=int, default=256)
-    ap.add_argument("--batch-target", type=int, default=0, help="work items aimed for per cluster (0 = default)")
+    ap.add_argument("--batch-per-wg", type=int, default=0, help="work items aimed for per workgroup (0 = default)")
     ap.add_argument("--batch-grid", type=int, default=0, help="persistent force workgroups (0 = resident)")
     ap.add_argument("--batch-itile", type=int, default=0, help="active rows per work item, 64 or 256 (0 = default)")
     ap.add_argument("--warm-time", type=float, default=1.0 / 64, help="batched: integrate to this time first")
     ap.add_argument("--autotune-steps", type=int, default=2, help="batched: steps per autotuned shape (0 = off)")
+    ap.add_argument("--skip-per-cluster", action="store_true", help="batched: skip the one-context-per-cluster run")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)

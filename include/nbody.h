@@ -256,19 +256,21 @@ nbody_status nbody_batch_energy(nbody_batch *b, const nbody_state *state, double
 nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out);
 
 /* Persistent force launch: force_grid workgroups (0 = as many as fit on the
- * device at once), target_items work items aimed for per cluster when its
- * active set is small (1..64, 0 = 16; the j-range is split to reach it) and
- * i_tile active rows per work item (64 or 256, 0 = 64).  Applies to later
- * steps and captures (a captured graph keeps the shape it was captured with).
- * Results depend on the shape only through the FP64 summation order of the
- * split partials (and, in MIXED mode, where the FP32 chunks start). */
-nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items, int32_t i_tile);
+ * device at once), items_per_wg work items aimed for per workgroup (1..16,
+ * 0 = 4: each step's padded work is cut into about force_grid * items_per_wg
+ * items of equal cost, at most 16384, by splitting each cluster's j-range
+ * into pieces of at least 512) and i_tile active rows per work item (64 or
+ * 256, 0 = 64).  Applies to later steps and captures (a captured graph keeps
+ * the shape it was captured with).  Results depend on the shape only through
+ * the FP64 summation order of the split partials (and, in MIXED mode, where
+ * the FP32 chunks start). */
+nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t items_per_wg, int32_t i_tile);
 
-/* The shape in use (HOST out[3]): force_grid, target_items, i_tile. */
+/* The shape in use (HOST out[3]): force_grid, items_per_wg, i_tile. */
 nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3]);
 
 /* Autotuner: times `steps` batched steps (after one untimed step) for each
- * i_tile in {64, 256} and target_items in {4, 8, 16, 32, 64} with HIP events,
+ * i_tile in {64, 256} and items_per_wg in {1, 2, 4, 8, 16} with HIP events,
  * and keeps the shape with the most pair interactions per second.  The
  * steps are real: the clusters advance by 11 * (steps + 1) batched steps
  * (fewer where they reach t_end).  Drops a captured graph (capture again). */

@@ -303,13 +303,13 @@ def nbody_batch_get_stats(b: int) -> nbody_stats:
     return s
 
 
-def nbody_batch_set_launch(b: int, force_grid: int = 0, target_items: int = 0, i_tile: int = 0) -> None:
-    _check(lib().nbody_batch_set_launch(C.c_void_p(b), int(force_grid), int(target_items), int(i_tile)),
+def nbody_batch_set_launch(b: int, force_grid: int = 0, items_per_wg: int = 0, i_tile: int = 0) -> None:
+    _check(lib().nbody_batch_set_launch(C.c_void_p(b), int(force_grid), int(items_per_wg), int(i_tile)),
            "nbody_batch_set_launch")
 
 
 def nbody_batch_get_launch(b: int):
-    """(force_grid, target_items, i_tile) in use."""
+    """(force_grid, items_per_wg, i_tile) in use."""
     out = (C.c_int32 * 3)()
     _check(lib().nbody_batch_get_launch(C.c_void_p(b), out), "nbody_batch_get_launch")
     return tuple(out)

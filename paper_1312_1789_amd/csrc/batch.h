@@ -6,7 +6,8 @@
 
 namespace nb {
 
-constexpr int kBatchMaxTarget = 64;   // largest items-per-cluster target the plan accepts
+constexpr int kBatchMaxItems = 16384;  // most work items the plan aims for in one step
+constexpr int kBatchMaxPerWG = 16;     // most items aimed for per persistent workgroup
 constexpr int kBatchITileMax = 256;   // largest i-tile: active rows per work item (= force workgroup size)
 constexpr int kBatchSchedBlock = 1024;  // particles per scheduling block
 
@@ -57,7 +58,8 @@ struct BatchLaunch {
     double eps2;
     int64_t n_hard;             // per cluster; every pair is unsoftened when eps2 == 0
     int force_grid;             // workgroups of the persistent force kernel
-    int target_items;           // work items aimed for per cluster
+    int per_wg;                 // work items aimed for per persistent workgroup
+    int k_items;                // items aimed for in one step: min(force_grid * per_wg, kBatchMaxItems)
     int itile;                  // active rows per work item: 64 or 256
 };
 

@@ -127,17 +127,22 @@ __device__ void block_scan(int64_t *v, int n, int64_t *sh)
 }
 
 // The plan of one batched step (one block).  For every cluster: active count
-// and offset, j-splits and work items; items are numbered in the cluster
-// order ord[] (largest clusters first) so the persistent force kernel starts
-// with the longest items.  Also resets the work queue and adds the step's
-// interactions to the counters.
+// and offset, j-splits and work items.  Items are sized by cost: the step's
+// padded work W = sum_c tiles_c * itile * N_c is cut into about k_items items
+// of W / k_items pair evaluations each (a cluster's j-range is split into s_c
+// pieces of at least 512), so no item is much longer than the average and the
+// persistent kernel ends evenly.  Items are numbered in the cluster order
+// ord[] (largest clusters first).  Bound used for the partial buffer:
+// s_c <= itile N_c k_items / W + 1, so sum_c s_c a_c <= itile k_items + n.
+// Also resets the work queue and adds the step's interactions to the counters.
 __global__ void __launch_bounds__(kBThreads)
 k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
-         const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int64_t *__restrict__ boff, BatchPlan *__restrict__ pl, int ncomp,
-         int target_items, int itile, BatchCounters *__restrict__ ctr)
+         const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int64_t *__restrict__ boff,
+         BatchPlan *__restrict__ pl, int ncomp, int k_items, int itile, BatchCounters *__restrict__ ctr)
 {
     __shared__ int64_t sh[kBThreads];
     // per-cluster active counts and block offsets inside the cluster
+    int64_t w = 0;
     for (int c = threadIdx.x; c < nc; c += kBThreads) {
         int64_t s = 0;
         for (int b = 0; b < nb; ++b) {
@@ -147,7 +152,17 @@ k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restr
         pl->nact[c] = s;
         pl->aoff[c] = s;
         if (s > 0) pl->tcur[c] = tnext[c];
+        w += (s + itile - 1) / itile * itile * (off[c + 1] - off[c]);
     }
+    // total padded work W (tree sum; integer, so order-free)
+    sh[threadIdx.x] = w;
+    __syncthreads();
+    for (int st = kBThreads / 2; st > 0; st >>= 1) {
+        if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    const int64_t W = sh[0];
+    const int64_t w_item = W / k_items + 1;
     __syncthreads();
     block_scan(pl->aoff, nc, sh);
     // splits, items (in rank order), partial rows (in cluster order)
@@ -155,7 +170,7 @@ k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restr
         const int c = ord[r];
         const int64_t na = pl->nact[c], nn = off[c + 1] - off[c];
         const int64_t tiles = (na + itile - 1) / itile;
-        int64_t sp = tiles > 0 ? (target_items + tiles - 1) / tiles : 0;
+        int64_t sp = (int64_t(itile) * nn + w_item - 1) / w_item;
         const int64_t sp_max = nn / 512 > 1 ? nn / 512 : 1;
         sp = sp < 1 ? 1 : (sp > sp_max ? sp_max : sp);
         int64_t jc = (nn + sp - 1) / sp;
@@ -450,7 +465,7 @@ hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_a
     hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, all_active,
                        L.plan, L.tnext, L.bcnt);
     hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.nb, L.off, L.ord, L.tnext, L.bcnt, L.boff,
-                       L.plan, 3 * (order / 2), L.target_items, L.itile, L.ctr);
+                       L.plan, 3 * (order / 2), L.k_items, L.itile, L.ctr);
     hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.boff,
                        all_active, L.plan, L.act);
     return hipGetLastError();

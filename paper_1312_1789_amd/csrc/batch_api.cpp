@@ -62,10 +62,9 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.tcur = take(nc * sizeof(int64_t));
     L.ctr = take(sizeof(nb::BatchCounters));
     L.act = take(n * sizeof(int32_t));
-    // split partials: a cluster with a active rows in t i-tiles of I rows
-    // takes s <= max(1, ceil(T / t)) splits, so s * a <= T * I + a; 12 components
-    // (the order-8 initialisation passes)
-    L.part = take(12 * (nc * size_t(nb::kBatchMaxTarget) * nb::kBatchITileMax + n) * sizeof(double));
+    // split partials: the plan keeps sum_c splits_c * active_c <= i_tile *
+    // items + n; 12 components (the order-8 initialisation passes)
+    L.part = take(12 * (size_t(nb::kBatchMaxItems) * nb::kBatchITileMax + n) * sizeof(double));
     L.force = take(12 * n * sizeof(double));
     L.rec = take(n * size_t(std::max(nb::record_bytes(c.order, c.precision), nb::record_bytes(8, NBODY_FP64))));
     L.energy = take(2 * size_t(sum_energy_blocks(off)) * sizeof(double));
@@ -228,7 +227,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.force = at<double>(b, lay.force);
     L.eps2 = cfg->eps2;
     L.n_hard = cfg->eps2 == 0.0 ? (int64_t(1) << 40) : cfg->n_hard;
-    L.target_items = 16;
+    L.per_wg = 4;
     L.itile = 64;
     nb::BatchPlan hp{};
     hp.queue = 0;
@@ -246,6 +245,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
         b->force_grid_req = 0;
         L.force_grid = nb::batch_force_resident(cfg->order, cfg->precision, L.itile, b->device);
         if (L.force_grid <= 0) e = hipErrorInvalidDeviceFunction;
+        L.k_items = std::min(L.force_grid * L.per_wg, nb::kBatchMaxItems);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(L.plan, &hp, sizeof(hp), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int64_t *>(L.off), b->off.data(), b->off.size() * sizeof(int64_t),
@@ -447,19 +447,20 @@ nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out)
     return NBODY_OK;
 }
 
-nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t target_items, int32_t i_tile)
+nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t per_wg, int32_t i_tile)
 {
     if (!b) return fail(NBODY_E_INVALID, "batch is NULL");
     if (force_grid < 0 || force_grid > (1 << 20)) return fail(NBODY_E_INVALID, "force_grid must be in [0, 2^20]");
-    if (target_items < 0 || target_items > nb::kBatchMaxTarget)
-        return fail(NBODY_E_INVALID, "target_items must be in [0, %d]", nb::kBatchMaxTarget);
+    if (per_wg < 0 || per_wg > nb::kBatchMaxPerWG)
+        return fail(NBODY_E_INVALID, "items_per_wg must be in [0, %d]", nb::kBatchMaxPerWG);
     if (i_tile != 0 && i_tile != 64 && i_tile != 256) return fail(NBODY_E_INVALID, "i_tile must be 0, 64 or 256");
     nb::BatchLaunch &L = b->L;
     L.itile = i_tile > 0 ? i_tile : 64;
-    L.target_items = target_items > 0 ? target_items : 16;
+    L.per_wg = per_wg > 0 ? per_wg : 4;
     b->force_grid_req = force_grid;
     L.force_grid = force_grid > 0 ? force_grid : nb::batch_force_resident(b->cfg.order, b->cfg.precision, L.itile, b->device);
     if (L.force_grid <= 0) return fail(NBODY_E_HIP, "occupancy query of the batched force kernel failed");
+    L.k_items = int(std::min<int64_t>(int64_t(L.force_grid) * L.per_wg, nb::kBatchMaxItems));
     return NBODY_OK;
 }
 
@@ -467,7 +468,7 @@ nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3])
 {
     if (!b || !out) return fail(NBODY_E_INVALID, "batch and out are required");
     out[0] = b->L.force_grid;
-    out[1] = b->L.target_items;
+    out[1] = b->L.per_wg;
     out[2] = b->L.itile;
     return NBODY_OK;
 }
@@ -486,7 +487,7 @@ nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *st, int32_t steps
         return fail(NBODY_E_HIP, "hipEventCreate failed");
     }
     const int itiles[2] = {64, 256};
-    const int targets[5] = {4, 8, 16, 32, 64};
+    const int targets[5] = {1, 2, 4, 8, 16};
     double best = -1.0;
     int best_i = 64, best_t = 16;
     nb::BatchCounters c0, c1;

@@ -206,8 +206,8 @@ class Batch:
         except Exception:
             pass
 
-    def set_launch(self, force_grid: int = 0, target_items: int = 0, i_tile: int = 0):
-        abi.nbody_batch_set_launch(self.b, force_grid, target_items, i_tile)
+    def set_launch(self, force_grid: int = 0, items_per_wg: int = 0, i_tile: int = 0):
+        abi.nbody_batch_set_launch(self.b, force_grid, items_per_wg, i_tile)
 
     def get_launch(self):
         return abi.nbody_batch_get_launch(self.b)
