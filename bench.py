@@ -17,6 +17,12 @@ number of block steps per cluster twice: through the batched entry points
 cluster (one nbody_step per cluster and block step).  Metric: aggregate pair
 interactions per second of each.
 
+A third workload, --workload microbench, times the force call alone
+(nbody_predict once, then nbody_force_block) on a King W0=6 model of
+N = 262144 for active sets N_act in {1, 16, 256, 4096, 65536, N} (random
+subsets), FP64 vs MIXED vs DS, and reports pair interactions/s, % of the
+VALU peak and the error against the oracle on sampled active rows.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -302,9 +308,126 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+MICRO_METRIC = "force call: pair interactions/s and % VALU peak per N_act, King W0=6 N=262144"
+
+
+def _time_launches(fn, min_ms=30.0, max_reps=50):
+    """Median duration (ms) of fn() from HIP events on the current stream."""
+    import torch
+    fn()
+    fn()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    fn()
+    s1.record()
+    torch.cuda.synchronize()
+    one = max(s0.elapsed_time(s1), 1e-3)
+    reps = int(min(max(3, min_ms / one), max_reps))
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), reps
+
+
+def run_microbench(args):
+    import torch
+    import nbody_ics
+    import oracle
+    from oracle import OracleConfig
+    from paper_1312_1789_amd import Simulation
+    n = args.micro_n
+    t0 = time.perf_counter()
+    model = nbody_ics.king(n, 6.0, 15)
+    d_all = nbody_ics.random_derivs(n, 1515, 8)
+    log("workload: King W0=6 n=%d (%.1f s to generate)" % (n, time.perf_counter() - t0))
+    sizes = [k for k in (1, 16, 256, 4096, 65536) if k < n] + [n]
+    orders = [int(o) for o in args.micro_orders.split(",")]
+    tick0 = 5 << 17
+    table = []
+    for order in orders:
+        d = d_all[: order - 2]
+        cfg = OracleConfig(order=order, eps2=1e-8)
+        acts = {k: nbody_ics.active_subset(n, k, 1500 + int(np.log2(k))) for k in sizes}
+        refs = {}
+        t0 = time.perf_counter()
+        for k in sizes:
+            rows = acts[k][: min(k, args.micro_rows)]
+            refs[k] = (rows, oracle.force(cfg, model.m, model.x, model.v, d[0] if order >= 6 else None,
+                                          d[1] if order >= 8 else None, act=rows, with_pot=False))
+        log("[micro] order %d: oracle rows %.1f s" % (order, time.perf_counter() - t0))
+        for prec in ("fp64", "mixed", "ds"):
+            sim = Simulation(model.m, model.x, model.v, order=order, precision=prec, eps2=1e-8, eta=0.1)
+            sim.load_state(model.x, model.v, d, np.full(n, tick0, np.int64), np.full(n, 3, np.int32))
+            sim.predict(tick0)
+            tuning = None
+            if args.micro_tune_max > 0:
+                t0 = time.perf_counter()
+                sim.autotune(args.micro_tune_max, 2)
+                tuning = sim.tuning()
+                log("[micro] p%d %s autotune %.1f s: %s" % (order, prec, time.perf_counter() - t0,
+                                                             [(r[0], r[1], r[2], r[3], r[4]) for r in tuning]))
+            peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+            for k in sizes:
+                act = torch.as_tensor(acts[k], device="cuda:0")
+                out = sim.alloc_forces(k)
+                ms, reps = _time_launches(lambda: sim.force_block(act, out, with_pot=False))
+                inter = float(k) * n
+                rate = inter / (ms * 1e-3)
+                tf = FLOPS_PER_INTERACTION[order] * rate / 1e12
+                rows, ref = refs[k]
+                pos = np.searchsorted(acts[k], rows)
+                err = {}
+                for key in ("acc", "jrk", "snp", "crk")[: order // 2]:
+                    g = out[key][:, pos].cpu().numpy()
+                    e = np.linalg.norm(g - ref[key], axis=0) / np.linalg.norm(ref[key], axis=0)
+                    err[key] = {"rms": float(np.sqrt(np.mean(e * e))), "max": float(e.max())}
+                shape = None
+                if tuning:
+                    r = next((r for r in tuning if r[0] >= k), tuning[-1])
+                    shape = {"ni": r[1], "block": r[2], "n_split": r[3], "jpath": r[4]}
+                row = {"order": order, "precision": prec, "n_act": k, "ms": ms, "reps": reps, "tuned_shape": shape,
+                       "interactions_per_s": rate, "tflops": tf, "frac_of_peak": tf / peak, "peak_tflops": peak,
+                       "error": err, "error_rows": int(len(rows))}
+                table.append(row)
+                log("[micro] p%d %-5s n_act %7d: %9.4f ms  %.3e int/s  %6.2f TF  %5.1f%% peak  acc rms %.1e jrk rms %.1e"
+                    % (order, prec, k, ms, rate, tf, 100 * tf / peak, err["acc"]["rms"], err["jrk"]["rms"]))
+            sim.close()
+            del sim
+    head = [r for r in table if r["precision"] == "mixed" and r["n_act"] == n and r["order"] == orders[0]][0]
+    line = {
+        "metric": MICRO_METRIC,
+        "value": head["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": 2,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "King W0=6 n=%d, stored derivatives seeded (|a| ~ 1), force call on random active "
+                               "subsets; flops per interaction %s" % (n, FLOPS_PER_INTERACTION),
+                   "n": n, "orders": orders},
+        "table": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["king1m", "batched"], default="king1m")
+    ap.add_argument("--workload", choices=["king1m", "batched", "microbench"], default="king1m")
+    ap.add_argument("--micro-n", type=int, default=262144)
+    ap.add_argument("--micro-orders", default="6")
+    ap.add_argument("--micro-rows", type=int, default=512, help="microbench: active rows checked against the oracle")
+    ap.add_argument("--micro-tune-max", type=int, default=65536,
+                    help="microbench: autotune the force launch up to this n_act first (0 = untuned defaults)")
     ap.add_argument("--clusters", type=int, default=256)
     ap.add_argument("--batch-per-wg", type=int, default=0, help="work items aimed for per workgroup (0 = default)")
     ap.add_argument("--batch-grid", type=int, default=0, help="persistent force workgroups (0 = resident)")
@@ -346,6 +469,9 @@ def main():
         del src, dst
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "microbench":
+        run_microbench(args)
         return
 
     t0 = time.perf_counter()

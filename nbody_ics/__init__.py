@@ -216,3 +216,11 @@ def kepler_pair(e: float = 0.5, a: float = 1.0, m1: float = 0.5, m2: float = 0.5
     x = np.stack([-m2 / M * rel_x, m1 / M * rel_x], axis=1)
     v = np.stack([-m2 / M * rel_v, m1 / M * rel_v], axis=1)
     return Model(np.array([m1, m2]), x, v)
+
+
+def random_derivs(n: int, seed: int, order: int) -> list:
+    """Seeded stand-ins for the stored acceleration derivatives a^(0..order-3)
+    of n particles, (3, n) each, with magnitudes typical of a cluster in Henon
+    units (|a| ~ 1, each higher derivative ~ 10 times the previous)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.normal(size=(3, n)) * 10.0 ** k for k in range(order - 2)]

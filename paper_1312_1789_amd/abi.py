@@ -40,6 +40,7 @@ EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
     "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
+    "nbody_autotune", "nbody_get_tuning",
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
     "nbody_batch_set_end", "nbody_batch_step", "nbody_batch_capture", "nbody_batch_replay", "nbody_batch_poll",
     "nbody_batch_last_step", "nbody_batch_energy", "nbody_batch_get_stats", "nbody_batch_set_launch",
@@ -98,6 +99,9 @@ def lib():
             "nbody_set_launch": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "nbody_set_timing": [P, C.c_int32],
             "nbody_get_timers": [P, C.POINTER(C.c_double), C.POINTER(I64)],
+            "nbody_autotune": [P, I64, C.c_int32],
+            "nbody_get_tuning": [P, C.c_int32, C.POINTER(I64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_int32)],
             "nbody_batch_workspace_size": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), C.POINTER(C.c_size_t)],
             "nbody_batch_create": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), P, C.c_size_t, P,
                                    C.POINTER(P)],
@@ -215,6 +219,22 @@ def nbody_set_launch(ctx: int, ni: int, block: int, n_split: int, jpath: int = 0
 
 def nbody_set_timing(ctx: int, enable: bool) -> None:
     _check(lib().nbody_set_timing(C.c_void_p(ctx), 1 if enable else 0), "nbody_set_timing")
+
+
+def nbody_autotune(ctx: int, max_n_act: int, reps: int = 3) -> None:
+    _check(lib().nbody_autotune(C.c_void_p(ctx), int(max_n_act), int(reps)), "nbody_autotune")
+
+
+def nbody_get_tuning(ctx: int):
+    """List of (n_act, ni, block, n_split, jpath, ms) rows of the tuned table."""
+    k = 32
+    na = (C.c_int64 * k)()
+    sh = (C.c_int32 * (4 * k))()
+    ms = (C.c_double * k)()
+    rows = C.c_int32(0)
+    _check(lib().nbody_get_tuning(C.c_void_p(ctx), k, na, sh, ms, C.byref(rows)), "nbody_get_tuning")
+    return [(int(na[r]), int(sh[4 * r]), int(sh[4 * r + 1]), int(sh[4 * r + 2]), int(sh[4 * r + 3]), float(ms[r]))
+            for r in range(rows.value)]
 
 
 PHASES = ("schedule", "host_roundtrip", "predict", "force", "correct")

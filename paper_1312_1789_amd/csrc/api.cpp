@@ -71,10 +71,26 @@ nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec
     a.out[3] = crk;
     a.out[4] = pot;
     a.part = ws_at<double>(ctx, ctx->lay.part);
-    a.ni = ctx->ni;
-    a.block = ctx->block;
-    a.n_split = ctx->n_split;
-    a.jpath = ctx->jpath;
+    if (ctx->manual) {
+        a.ni = ctx->ni;
+        a.block = ctx->block;
+        a.n_split = ctx->n_split;
+        a.jpath = ctx->jpath;
+    } else if (ctx->tuned) {
+        // the smallest tuned bucket that holds n_act (else the largest)
+        int r = 0;
+        while (r + 1 < ctx->n_tune && ctx->tune[r].n_act < n_act) ++r;
+        a.ni = ctx->tune[r].ni;
+        a.block = ctx->tune[r].block;
+        a.n_split = ctx->tune[r].n_split;
+        a.jpath = ctx->tune[r].jpath;
+    } else {
+        // untuned default: workgroups no wider than the active set needs
+        a.ni = 1;
+        a.block = n_act <= 64 ? 64 : (n_act <= 128 ? 128 : 256);
+        a.n_split = 0;
+        a.jpath = 0;
+    }
     int used = 0;
     NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
     ctx->stats.interactions += double(n_act) * double(ctx->cfg.n);
@@ -168,6 +184,10 @@ nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes
     ctx->ni = 1;
     ctx->block = 256;
     ctx->n_split = 0;
+    ctx->jpath = 0;
+    ctx->manual = false;
+    ctx->tuned = false;
+    ctx->n_tune = 0;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipMemsetAsync(scalars(ctx), 0, sizeof(nb::DevScalars), ctx->stream);
@@ -218,6 +238,109 @@ nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t
     ctx->block = block;
     ctx->n_split = n_split;
     ctx->jpath = jpath;
+    ctx->manual = true;
+    return NBODY_OK;
+}
+
+nbody_status nbody_autotune(nbody_ctx *ctx, int64_t max_n_act, int32_t reps)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (!ctx->predicted) return fail(NBODY_E_STATE, "nbody_autotune before nbody_predict");
+    if (max_n_act < 1) return fail(NBODY_E_INVALID, "max_n_act must be >= 1");
+    if (reps < 1 || reps > 1000) return fail(NBODY_E_INVALID, "reps must be in [1, 1000]");
+    const nbody_config &c = ctx->cfg;
+    const int64_t top = max_n_act < c.n ? max_n_act : c.n;
+    std::vector<int64_t> sizes;
+    for (int64_t k = 1; k <= top && int(sizes.size()) < nb::kTuneRows - 1; k *= 2) sizes.push_back(k);
+    if (sizes.back() != top) sizes.push_back(top);
+    int32_t *all = ws_at<int32_t>(ctx, ctx->lay.act);
+    NB_HIP(nb::launch_iota(c.n, all, ctx->stream));
+    double *F = ws_at<double>(ctx, ctx->lay.force);
+    const int64_t n = c.n;
+    hipEvent_t e0, e1;
+    NB_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(NBODY_E_HIP, "hipEventCreate failed");
+    }
+    nbody_status st = NBODY_OK;
+    int rows = 0;
+    for (int64_t na : sizes) {
+        nb::TuneRow best{na, 1, 256, 0, 0, 1e300};
+        for (int ni : {1, 2})
+            for (int block : {64, 128, 256})
+                for (int jpath : {1, 2}) {
+                    const int base = nb::auto_split(n, na, ni, block);
+                    int prev = -1;
+                    for (int mult : {1, 2, 4}) {   // splits base / 2, base, base * 2
+                        int sp = mult == 1 ? base / 2 : (mult == 2 ? base : base * 2);
+                        sp = sp < 1 ? 1 : (sp > 65535 ? 65535 : sp);
+                        if (int64_t(sp) * na > nb::kPartEntries) sp = int(nb::kPartEntries / na);
+                        if (sp == prev) continue;
+                        prev = sp;
+                        nb::ForceArgs a{};
+                        a.rec = ctx->ws + ctx->lay.rec;
+                        a.n = n;
+                        a.act = all;
+                        a.n_act = na;
+                        a.eps2 = c.eps2;
+                        a.n_hard = hard_count(c);
+                        a.out[0] = F;
+                        a.out[1] = F + 3 * n;
+                        a.out[2] = c.order >= 6 ? F + 6 * n : nullptr;
+                        a.out[3] = c.order >= 8 ? F + 9 * n : nullptr;
+                        a.out[4] = nullptr;
+                        a.part = ws_at<double>(ctx, ctx->lay.part);
+                        a.ni = ni;
+                        a.block = block;
+                        a.n_split = sp;
+                        a.jpath = jpath;
+                        hipError_t e = nb::launch_force(c.order, c.precision, a, ctx->stream, nullptr);
+                        if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+                        for (int r = 0; e == hipSuccess && r < reps; ++r)
+                            e = nb::launch_force(c.order, c.precision, a, ctx->stream, nullptr);
+                        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0.0f;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        if (e != hipSuccess) {
+                            st = fail(NBODY_E_HIP, "nbody_autotune: %s", hipGetErrorString(e));
+                            break;
+                        }
+                        const double per = double(ms) / reps;
+                        if (per < best.ms) best = nb::TuneRow{na, ni, block, sp, jpath, per};
+                    }
+                    if (st != NBODY_OK) break;
+                }
+        if (st != NBODY_OK) break;
+        ctx->tune[rows++] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != NBODY_OK) return st;
+    ctx->n_tune = rows;
+    ctx->tuned = true;
+    ctx->manual = false;
+    return NBODY_OK;
+}
+
+nbody_status nbody_get_tuning(nbody_ctx *ctx, int32_t max_rows, int64_t *n_act, int32_t *shape, double *ms,
+                              int32_t *rows)
+{
+    if (!ctx || !rows) return fail(NBODY_E_INVALID, "ctx and rows are required");
+    if (max_rows < 0) return fail(NBODY_E_INVALID, "max_rows must be >= 0");
+    const int r = ctx->tuned ? (ctx->n_tune < max_rows ? ctx->n_tune : max_rows) : 0;
+    for (int k = 0; k < r; ++k) {
+        if (n_act) n_act[k] = ctx->tune[k].n_act;
+        if (shape) {
+            shape[4 * k + 0] = ctx->tune[k].ni;
+            shape[4 * k + 1] = ctx->tune[k].block;
+            shape[4 * k + 2] = ctx->tune[k].n_split;
+            shape[4 * k + 3] = ctx->tune[k].jpath;
+        }
+        if (ms) ms[k] = ctx->tune[k].ms;
+    }
+    *rows = ctx->tuned ? ctx->n_tune : 0;
     return NBODY_OK;
 }
 

@@ -323,7 +323,7 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
         }
         hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
         const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
-        lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, tile, acc);
+        lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
         if (q0 < na) {
             double *dst = part + pl->poff[c] + split * ncomp * na;
 #pragma unroll

@@ -25,12 +25,11 @@ namespace {
 // j-split [split * j_chunk, min(n, (split+1) * j_chunk)).  Pairs with both
 // indices below n_hard are unsoftened and their self pair is masked; above
 // n_hard the self pair is evaluated with eps2 > 0 (its acceleration and
-// derivatives are exactly zero, every difference being zero) and its
-// potential term is removed at the end.
+// derivatives are exactly zero, every difference being zero), except in the
+// kernels that also sum the potential, which mask it by index.
 template <class Pol, int P, int NI>
-__device__ __forceinline__ void store_rows(const typename Pol::Rec *__restrict__ rec, int64_t n_act, int64_t row0,
-                                           int split, int n_split, int64_t js0, int64_t j1, double eps2,
-                                           const int64_t *iidx, double (*acc)[13], double *__restrict__ o_acc,
+__device__ __forceinline__ void store_rows(int64_t n_act, int64_t row0, int split, int n_split,
+                                           double (*acc)[13], double *__restrict__ o_acc,
                                            double *__restrict__ o_jrk, double *__restrict__ o_snp,
                                            double *__restrict__ o_crk, double *__restrict__ o_pot,
                                            double *__restrict__ part)
@@ -40,9 +39,7 @@ __device__ __forceinline__ void store_rows(const typename Pol::Rec *__restrict__
     for (int k = 0; k < NI; ++k) {
         const int64_t q = row0 + int64_t(k) * blockDim.x;
         if (q >= n_act) continue;
-        const int64_t i = iidx[k];
-        double pot = acc[k][kPot];
-        if (Pol::kWithPot && i >= js0 && i < j1) pot -= Pol::self_pot(rec[i], eps2);  // self pair was in the softened loop
+        const double pot = acc[k][kPot];
         if (n_split == 1) {
             double *outs[4] = {o_acc, o_jrk, o_snp, o_crk};
 #pragma unroll
@@ -100,11 +97,15 @@ k_force(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *__r
         for (int64_t j = jc; j < je; ++j) {
             const Rec rj = rec[j];
 #pragma unroll
-            for (int k = 0; k < NI; ++k) Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
+            for (int k = 0; k < NI; ++k) {
+                // the self pair adds nothing to a, jerk, ...; only the potential needs it masked
+                if constexpr (Pol::kWithPot) Pol::template pair<true>(ip[k], rj, e2, j != iidx[k], p[k]);
+                else Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
+            }
         }
         flush<Part, NI>(p, acc);
     }
-    store_rows<Pol, P, NI>(rec, n_act, row0, split, n_split, js0, j1, eps2, iidx, acc, o_acc, o_jrk, o_snp, o_crk,
+    store_rows<Pol, P, NI>(n_act, row0, split, n_split, acc, o_acc, o_jrk, o_snp, o_crk,
                            o_pot, part);
 }
 
@@ -139,13 +140,17 @@ k_force_lds(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t 
     hard_pairs<Pol, NI>(rec, j0, (j1 < n_hard) ? j1 : n_hard, 0, n_hard, e2, ip, iidx, acc);
 
     const int64_t js0 = (j0 > n_hard) ? j0 : n_hard;
-    lds_tiles<Pol, NI, BLOCK, UNROLL, TILE>(rec, js0, j1, e2, ip, tile, acc);
-    store_rows<Pol, P, NI>(rec, n_act, row0, split, n_split, js0, j1, eps2, iidx, acc, o_acc, o_jrk, o_snp, o_crk,
+    lds_tiles<Pol, NI, BLOCK, UNROLL, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
+    store_rows<Pol, P, NI>(n_act, row0, split, n_split, acc, o_acc, o_jrk, o_snp, o_crk,
                            o_pot, part);
 }
 
-// Sum of the j-split partial results in split order.
-template <int P>
+// Sum of the j-split partial results.  A group of L lanes (L = 1, 4, 16 or
+// 64, consecutive lanes of one wavefront) owns one output value: lane l adds
+// splits l, l + L, l + 2L, ... in order, then the group folds its L sums with
+// a fixed butterfly of cross-lane exchanges.  The order depends only on
+// n_split and L, so reruns are bitwise identical.
+template <int P, int L>
 __global__ void __launch_bounds__(256)
 k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__restrict__ o_acc,
          double *__restrict__ o_jrk, double *__restrict__ o_snp, double *__restrict__ o_crk,
@@ -153,12 +158,18 @@ k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__
 {
     constexpr int NV = 3 * (P / 2);
     constexpr int NC = NV + 1;
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n_act * NC) return;
-    const int c = int(t / n_act);
-    const int64_t q = t - int64_t(c) * n_act;
+    const int64_t g = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / L;   // output index
+    const int l = int(threadIdx.x) % L;
+    const bool valid = g < n_act * NC;
+    const int64_t gg = valid ? g : 0;
+    const int c = int(gg / n_act);
+    const int64_t q = gg - int64_t(c) * n_act;
     double s = 0.0;
-    for (int sp = 0; sp < n_split; ++sp) s += part[(int64_t(sp) * NC + c) * n_act + q];
+    if (valid)
+        for (int sp = l; sp < n_split; sp += L) s += part[(int64_t(sp) * NC + c) * n_act + q];
+#pragma unroll
+    for (int m = L / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (!valid || l != 0) return;
     if (c == NV) {
         if (o_pot) o_pot[q] = s;
         return;
@@ -166,6 +177,23 @@ k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__
     double *outs[4] = {o_acc, o_jrk, o_snp, o_crk};
     double *o = outs[c / 3];
     if (o) o[(c % 3) * n_act + q] = s;
+}
+
+template <int P>
+hipError_t launch_reduce(const ForceArgs &a, int n_split, hipStream_t s)
+{
+    const int64_t outs = a.n_act * (3 * (P / 2) + 1);
+    // lanes per output: enough that each lane adds at most about 8 splits
+    const int L = n_split <= 8 ? 1 : n_split <= 32 ? 4 : n_split <= 128 ? 16 : 64;
+    const unsigned blocks = unsigned((outs * L + 255) / 256);
+#define NB_RED(LL) hipLaunchKernelGGL((k_reduce<P, LL>), dim3(blocks), dim3(256), 0, s, a.part, a.n_act, n_split, \
+                                      a.out[0], a.out[1], a.out[2], a.out[3], a.out[4])
+    if (L == 1) NB_RED(1);
+    else if (L == 4) NB_RED(4);
+    else if (L == 16) NB_RED(16);
+    else NB_RED(64);
+#undef NB_RED
+    return hipGetLastError();
 }
 
 struct Shape {
@@ -194,10 +222,7 @@ hipError_t run(const ForceArgs &a, hipStream_t s, const Shape &sh)
 #undef NB_FORCE_ARGS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sh.n_split == 1) return e;
-    const int64_t work = a.n_act * (3 * (P / 2) + 1);
-    hipLaunchKernelGGL((k_reduce<P>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, s, a.part, a.n_act,
-                       sh.n_split, a.out[0], a.out[1], a.out[2], a.out[3], a.out[4]);
-    return hipGetLastError();
+    return launch_reduce<P>(a, sh.n_split, s);
 }
 
 template <class Pol, int P>
@@ -235,7 +260,7 @@ int record_bytes(int order, int precision)
 // Number of j-splits: enough waves to cover every SIMD several times when the
 // active set is small, bounded by the partial-sum scratch and by keeping at
 // least 256 j per split.
-static int auto_split(int64_t n, int64_t n_act, int ni, int block)
+int auto_split(int64_t n, int64_t n_act, int ni, int block)
 {
     const int64_t per_block = int64_t(block) * ni;
     const int64_t tiles = (n_act + per_block - 1) / per_block;

@@ -89,6 +89,18 @@ struct ForceArgs {
 
 hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split);
 
+// j-splits that give about 8 waves per SIMD for n_act rows in workgroups of
+// `block` lanes with ni rows per lane (the default when n_split is 0).
+int auto_split(int64_t n, int64_t n_act, int ni, int block);
+
+// One row of the force-launch table filled by nbody_autotune.
+struct TuneRow {
+    int64_t n_act;
+    int ni, block, n_split, jpath;
+    double ms;
+};
+constexpr int kTuneRows = 32;
+
 // Pack FP64 order-8 records {x, m, v, a, j} from state arrays (a, j may be null = 0).
 hipError_t launch_pack_f64(int64_t n, const double *m, const double *x, const double *v, const double *a,
                            const double *j, void *rec, hipStream_t s);
@@ -127,7 +139,11 @@ struct nbody_ctx {
     nb::Layout lay;
     int device;
     bool predicted;
-    int ni, block, n_split, jpath;
+    int ni, block, n_split, jpath;   // launch shape fixed by nbody_set_launch (when manual)
+    bool manual;
+    bool tuned;                       // tune[] filled by nbody_autotune
+    int n_tune;
+    nb::TuneRow tune[nb::kTuneRows];
     nbody_stats stats;
     bool timing;              // record phase events in nbody_step
     hipEvent_t ev[6];         // phase boundaries (created on first enable)

@@ -105,7 +105,6 @@ template <int P, bool POT> struct PolF64 {
         if (MASK) mr = valid ? mr : 0.0;
         core_fma<P, POT, double>(dx, dy, dz, wx, wy, wz, ex, ey, ez, fx, fy, fz, mr, rinv * rinv, A);
     }
-    __device__ static double self_pot(const Rec &r, double eps2) { return r.m * rsqrt64(eps2); }
 };
 
 // Double-single inputs shared by the MIXED and DS policies: positions and
@@ -145,13 +144,6 @@ template <int P> struct DSIn {
         if (MASK) mr = valid ? mr : 0.0f;
         core_fma<P, POT, float>(dx, dy, dz, wx, wy, wz, ex, ey, ez, fx, fy, fz, mr, rinv * rinv, A);
     }
-    // the self pair's potential term, computed exactly as in the loop
-    __device__ static double self_pot(const RecDS<P> &r, double eps2)
-    {
-        const float e2 = float(eps2);
-        const float r2 = __builtin_fmaf(0.0f, 0.0f, __builtin_fmaf(0.0f, 0.0f, __builtin_fmaf(0.0f, 0.0f, e2)));
-        return double(r.m * __builtin_amdgcn_rsqf(r2));
-    }
 };
 
 // MIXED policy: FP32 arithmetic on double-single differences, FP32 partial
@@ -170,7 +162,6 @@ template <int P, bool POT> struct PolMx {
     {
         DSIn<P>::template terms<MASK, POT>(i, j, eps2, valid, A);
     }
-    __device__ static double self_pot(const Rec &r, double eps2) { return DSIn<P>::self_pot(r, eps2); }
 };
 
 // DS policy: no FP64 instruction in the j loop; every term is added into a
@@ -210,7 +201,6 @@ template <int P, bool POT> struct PolDS {
         for (int c = 0; c < nv; ++c) two_sum_add(A[c], T[c]);
         if constexpr (POT) two_sum_add(A[kPot], T[kPot]);
     }
-    __device__ static double self_pot(const Rec &r, double eps2) { return DSIn<P>::self_pot(r, eps2); }
 };
 
 template <class Part> __device__ __forceinline__ void zero_part(Part &p) { p = Part(0); }
@@ -282,7 +272,7 @@ __device__ __forceinline__ void flush(Part (*p)[13], double (*acc)[13])
 // from js0.  Every thread of the block must call it (it synchronises).
 template <class Pol, int NI, int BLOCK, int UNROLL, int TILE>
 __device__ __forceinline__ void lds_tiles(const typename Pol::Rec *__restrict__ rec, int64_t js0, int64_t j1,
-                                          typename Pol::ET e2, const typename Pol::I *ip,
+                                          typename Pol::ET e2, const typename Pol::I *ip, const int64_t *iidx,
                                           typename Pol::Rec (*tile)[TILE], double (*acc)[13])
 {
     using Rec = typename Pol::Rec;
@@ -336,8 +326,14 @@ __device__ __forceinline__ void lds_tiles(const typename Pol::Rec *__restrict__ 
 #pragma unroll UNROLL
             for (int u = 0; u < seg; ++u) {
                 const Rec rj = tr[jj + u];
+                const int64_t j = jt + jj + u;
 #pragma unroll
-                for (int k = 0; k < NI; ++k) Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
+                for (int k = 0; k < NI; ++k) {
+                    // the self pair adds nothing to a, jerk, ...; only the
+                    // potential needs it masked
+                    if constexpr (Pol::kWithPot) Pol::template pair<true>(ip[k], rj, e2, j != iidx[k], p[k]);
+                    else Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
+                }
             }
             jj += seg;
             since += seg;

@@ -72,6 +72,13 @@ class Simulation:
     def set_launch(self, ni: int = 1, block: int = 256, n_split: int = 0, jpath: int = 0):
         abi.nbody_set_launch(self.ctx, ni, block, n_split, jpath)
 
+    def autotune(self, max_n_act: int = 16384, reps: int = 3):
+        """Tune the force launch per active size on the last prediction."""
+        abi.nbody_autotune(self.ctx, max_n_act, reps)
+
+    def tuning(self):
+        return abi.nbody_get_tuning(self.ctx)
+
     def set_timing(self, enable: bool = True):
         abi.nbody_set_timing(self.ctx, enable)
 

@@ -42,10 +42,7 @@ def physical_derivs(m, x, v, eps2, n_hard):
 
 
 def random_derivs(n, seed, order):
-    """Seeded derivative inputs a^(0..order-3) with magnitudes typical of a
-    cluster in Henon units (|a| ~ 1, higher derivatives ~ 10^k)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    return [rng.normal(size=(3, n)) * 10.0 ** k for k in range(order - 2)]
+    return nbody_ics.random_derivs(n, seed, order)
 
 
 def oracle_force(order, eps2, n_hard, m, x, v, a=None, j=None, act=None):

@@ -113,6 +113,33 @@ def test_launch_shapes_and_determinism(small_case, precision):
     assert np.max(rel_err(one, ref["acc"])) < (1e-12 if precision == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuned_launch_keeps_parity(small_case, precision):
+    """nbody_autotune fills one row per power-of-two active size with a valid
+    shape; force calls then take their shape from the table and still match
+    the oracle; a shape set afterwards replaces the table."""
+    model, eps2, n_hard, d = small_case
+    n = model.n
+    sim = _sim(model, 6, precision, eps2, n_hard, d)
+    sim.autotune(1024, 1)
+    table = sim.tuning()
+    say("tuned table (%s): %s" % (precision, [(r[0], r[1], r[2], r[3], r[4], round(r[5], 4)) for r in table]))
+    assert [r[0] for r in table] == [1 << k for k in range(11)]
+    for na, ni, block, sp, jpath, ms in table:
+        assert ni in (1, 2) and block in (64, 128, 256) and jpath in (1, 2) and sp >= 1 and ms > 0
+    for k in (1, 17, 300, 2999):
+        act = nbody_ics.active_subset(n, k, 1540 + k)
+        out = sim.force_block(torch.as_tensor(act, device=sim.device))
+        ref = oracle_force(6, eps2, n_hard, model.m, model.x, model.v, d[0], d[1], act=act)
+        _check(out, ref, 6, precision, act.size)
+    act = torch.as_tensor(nbody_ics.active_subset(n, 700, 1530), device=sim.device)
+    sim.set_launch(2, 128, 5, 2)
+    a1 = sim.force_block(act)["acc"].cpu().numpy()
+    sim.set_launch(1, 64, 5, 1)
+    a2 = sim.force_block(act)["acc"].cpu().numpy()
+    np.testing.assert_array_equal(a1, a2)
+
+
 def test_unsoftened_pair_and_empty_call():
     """eps = 0 (every pair unsoftened, self pair excluded by index): the
     two-body closed form; n_act = 0 is a no-op."""
