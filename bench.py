@@ -67,9 +67,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_act: int, n: int):
+def read_traffic(n_act: int, n: int, shape):
     """HBM bytes per force launch from the committed counter summary, or None
-    when it is missing or was taken on a different force-kernel source."""
+    when it is missing or was taken on a different force-kernel source or
+    launch shape."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     vals = {}
@@ -81,13 +82,25 @@ def read_traffic(n_act: int, n: int):
         return None
     if int(vals.get("n", -1)) != n or int(vals.get("n_act", -1)) != n_act:
         return None
+    if shape is None or vals.get("launch") != "%d,%d,%d,%d" % (shape["ni"], shape["block"], shape["n_split"],
+                                                               shape["jpath"]):
+        return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
 
-def run_precision(model, precision, order, steps, warmup, level):
+def kernel_name(shape, order):
+    """The force kernel a MIXED launch shape runs (scalar or LDS j path)."""
+    if shape is None:
+        return "k_force_lds<PolMx<%d>> (MIXED pairwise force, default shape)" % order
+    k = "k_force" if shape["jpath"] == 1 else "k_force_lds"
+    return "%s<PolMx<%d>, ni=%d> block %d, %d j-splits (MIXED pairwise force)" % (
+        k, order, shape["ni"], shape["block"], shape["n_split"])
+
+
+def run_precision(model, precision, order, steps, warmup, level, tune_max, force_shape=None):
     import torch
     from paper_1312_1789_amd import Simulation
     sim = Simulation(model.m, model.x, model.v, order=order, precision=precision, eps2=1e-8, eta=0.1,
@@ -96,6 +109,21 @@ def run_precision(model, precision, order, steps, warmup, level):
     sim.init()
     torch.cuda.synchronize()
     log("[%s] init (two FP64 force passes) %.2f s" % (precision, time.perf_counter() - t0))
+    shape = None
+    if force_shape:
+        ni, block, n_split, jpath = force_shape
+        sim.set_launch(ni, block, n_split, jpath)
+        shape = {"ni": ni, "block": block, "n_split": n_split, "jpath": jpath, "set_by": "--force-shape"}
+        log("[%s] force launch shape set: %s" % (precision, shape))
+    elif tune_max > 0:
+        t0 = time.perf_counter()
+        sim.predict(0)
+        sim.autotune(tune_max, 2)
+        table = sim.tuning()
+        r = table[-1]
+        shape = {"ni": r[1], "block": r[2], "n_split": r[3], "jpath": r[4], "tuned_up_to_n_act": r[0]}
+        log("[%s] autotune up to n_act %d: %.1f s; shape for the full active set %s"
+            % (precision, r[0], time.perf_counter() - t0, shape))
     for w in range(warmup):
         t, na = sim.step()
         log("[%s] warmup step %d: tick %d n_act %d" % (precision, w, t, na))
@@ -114,7 +142,7 @@ def run_precision(model, precision, order, steps, warmup, level):
     log("[%s] %d steps: %.1f ms/step, %.4e interactions/s; phases (ms/step) %s"
         % (precision, steps, ms_step, inter / wall, {k: round(v / nt, 3) for k, v in phases.items()}))
     return sim, {"ms_per_step": ms_step, "interactions_per_s": inter / wall, "n_act_per_step": n_act_sum / steps,
-                 "phase_ms_per_step": {k: v / nt for k, v in phases.items()}}
+                 "phase_ms_per_step": {k: v / nt for k, v in phases.items()}, "launch": shape}
 
 
 def cpu_baseline_and_error(model, sims, order, target_s):
@@ -442,6 +470,14 @@ def main():
     ap.add_argument("--order", type=int, default=6)
     ap.add_argument("--level", type=int, default=10, help="shared block level (dt = 2^-level)")
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
+    # default shapes: what nbody_autotune selects for this workload on MI355X
+    # (fixed here so that the timed kernel is the profiled one); "" = autotune
+    ap.add_argument("--force-shape-mixed", default="1,64,16,1",
+                    help="ni,block,n_split,jpath of the MIXED force ('' = autotune up to --tune-max)")
+    ap.add_argument("--force-shape-fp64", default="2,128,32,1",
+                    help="ni,block,n_split,jpath of the FP64 force ('' = autotune up to --tune-max)")
+    ap.add_argument("--tune-max", type=int, default=65536,
+                    help="autotune the force launch up to this n_act before timing (0 = untuned defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -480,7 +516,9 @@ def main():
 
     sims, res = {}, {}
     for prec, k in (("mixed", args.steps), ("fp64", args.fp64_steps or args.steps)):
-        sims[prec], res[prec] = run_precision(model, prec, args.order, k, args.warmup, args.level)
+        fs = args.force_shape_mixed if prec == "mixed" else args.force_shape_fp64
+        fs = tuple(int(v) for v in fs.split(",")) if fs else None
+        sims[prec], res[prec] = run_precision(model, prec, args.order, k, args.warmup, args.level, args.tune_max, fs)
 
     n = args.n
     mixed = res["mixed"]
@@ -488,10 +526,11 @@ def main():
     n_act = int(round(mixed["n_act_per_step"]))
     flops_launch = FLOPS_PER_INTERACTION[args.order] * float(n_act) * n
     achieved = flops_launch / (force_ms * 1e-3) / 1e12
-    traffic = read_traffic(n_act, n)
+    traffic = read_traffic(n_act, n, mixed["launch"])
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_force_lds<PolMx<6>> (MIXED 6th-order pairwise force)",
+                "kernel": kernel_name(mixed["launch"], args.order),
+                "launch": mixed["launch"],
                 "flops_per_interaction": FLOPS_PER_INTERACTION[args.order],
                 "force_ms_per_launch": round(force_ms, 3),
                 "frac_literature_97_flops": round(achieved * FLOPS_LITERATURE[args.order]
