@@ -23,6 +23,11 @@ N = 262144 for active sets N_act in {1, 16, 256, 4096, 65536, N} (random
 subsets), FP64 vs MIXED vs DS, and reports pair interactions/s, % of the
 VALU peak and the error against the oracle on sampled active rows.
 
+Two integration workloads: --workload c2 (Plummer N = 131072, 6th order,
+FP64 vs MIXED to t_end, with the active-block histogram, whole-run
+interactions/s and energy drift) and --workload c3 (King W0=7 with 2^20 stars
+plus a black-hole binary, 8th order, MIXED, a short run).
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -448,9 +453,155 @@ def run_microbench(args):
     print(json.dumps(line), flush=True)
 
 
+def integrate_run(model, label, t_end_tick, **kw):
+    """Integrate a Simulation to t_end_tick with nbody_step; returns the run
+    record (steps, interactions/s, N_act histogram, energies, phase times)."""
+    import torch
+    from paper_1312_1789_amd import Simulation
+    sim = Simulation(model.m, model.x, model.v, **kw)
+    sim.init()
+    E0 = sum(sim.energy())
+    sim.predict(0)
+    sim.autotune(min(65536, model.n), 2)
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    hist = np.zeros(32)
+    whist = np.zeros(32)
+    steps, n_act_sum = 0, 0
+    t0 = time.perf_counter()
+    last = t0
+    while True:
+        nxt = int((sim.t_tick + (torch.ones_like(sim.t_tick) << (20 - sim.level.to(torch.int64)))).min())
+        if nxt > t_end_tick:
+            break
+        t, na = sim.step()
+        steps += 1
+        n_act_sum += na
+        b = int(np.log2(na))
+        hist[b] += 1
+        whist[b] += float(na) * model.n
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log("[%s] t = %.5f, %d steps" % (label, t / 2.0 ** 20, steps))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    E1 = sum(sim.energy())
+    st = sim.stats()
+    phases, nt = sim.timers()
+    rec = {"steps": steps, "wall_s": wall, "interactions": st.interactions,
+           "interactions_per_s": st.interactions / wall, "mean_n_act": n_act_sum / max(steps, 1),
+           "dE_over_E": (E1 - E0) / E0, "dt_rule": sim.dt_rule, "dt_underflow": st.dt_underflow,
+           "phase_ms_total": phases,
+           "n_act_hist_log2": {"bins": [int(2 ** b) for b in range(32) if hist[b] > 0],
+                               "steps": [int(hist[b]) for b in range(32) if hist[b] > 0],
+                               "interaction_share": [float(whist[b] / whist.sum()) for b in range(32) if hist[b] > 0]}}
+    log("[%s] %d steps to t = %.4f in %.1f s: %.4e interactions/s (whole steps), mean n_act %.0f, |dE/E| %.3e, "
+        "rule %d, phases (s) %s" % (label, steps, t_end_tick / 2.0 ** 20, wall, rec["interactions_per_s"],
+                                    rec["mean_n_act"], abs(rec["dE_over_E"]), sim.dt_rule,
+                                    {k: round(v / 1e3, 2) for k, v in phases.items()}))
+    return sim, rec
+
+
+def integrate_batched_one(model, t_end_tick, kw):
+    """The same integration through the batched entry points with a single
+    cluster: block steps replayed from a captured graph, no host round trip
+    per step (the host polls every 256 replays)."""
+    import torch
+    from paper_1312_1789_amd import Batch
+    B = Batch([(model.m, model.x, model.v)], precision="mixed", **kw)
+    B.init()
+    E0 = sum(t + w for t, w in zip(*B.energy()))
+    h0 = B.to_numpy()
+    B.set_end(t_end_tick)
+    B.autotune(2)
+    # the autotuner's steps are real: restart from the initial state for the timed run
+    B.load_state(h0)
+    B.capture()
+    B.synchronize()
+    s0 = B.stats()
+    t0 = time.perf_counter()
+    while True:
+        B.replay(256)
+        live, tcur = B.poll()
+        if live == 0:
+            break
+    wall = time.perf_counter() - t0
+    s1 = B.stats()
+    E1 = sum(t + w for t, w in zip(*B.energy()))
+    steps = s1.steps - s0.steps
+    rec = {"steps_incl_idle_replays": steps, "wall_s": wall, "interactions": s1.interactions - s0.interactions,
+           "interactions_per_s": (s1.interactions - s0.interactions) / wall, "dE_over_E": (E1 - E0) / E0,
+           "dt_underflow": s1.dt_underflow, "launch": B.get_launch(), "t_end_reached": tcur[0] / 2.0 ** 20}
+    log("[mixed, one-cluster batch, graph] %d replays in %.1f s: %.4e interactions/s, |dE/E| %.3e, shape %s"
+        % (steps, wall, rec["interactions_per_s"], abs(rec["dE_over_E"]), rec["launch"]))
+    B.close()
+    return rec
+
+
+def run_c2(args):
+    import nbody_ics
+    n = args.c2_n
+    model = nbody_ics.plummer(n, 12)
+    t_end = int(args.c2_t_end * 2 ** 20)
+    log("workload: Plummer n=%d, 6th order, eta 0.1, to t = %.4f" % (n, t_end / 2.0 ** 20))
+    kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
+    runs = {}
+    for label, prec, rule in (("mixed", "mixed", 0), ("fp64_rule_order4", "fp64", 2), ("fp64", "fp64", 0)):
+        sim, runs[label] = integrate_run(model, label, t_end, precision=prec, dt_rule=rule, **kw)
+        sim.close()
+        del sim
+    runs["mixed_one_cluster_graph"] = integrate_batched_one(model, t_end, kw)
+    mixed = runs["mixed"]
+    line = {
+        "metric": "C2: whole-run pair interactions/s, Plummer N=131072, 6th order, MIXED vs FP64",
+        "value": mixed["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1, "steps": mixed["steps"],
+        "warmup": 0, "ms_per_step": mixed["wall_s"] / max(mixed["steps"], 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "Plummer n=%d (seed 12), eps = 1e-4, 6th-order Hermite block steps, eta = 0.1, "
+                               "t = 0 -> %.4f" % (n, t_end / 2.0 ** 20), "n": n, "order": 6},
+        "runs": runs,
+        "mixed_over_fp64_same_rule": mixed["interactions_per_s"] / runs["fp64_rule_order4"]["interactions_per_s"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_c3(args):
+    import torch
+    import nbody_ics
+    n_stars = args.c3_stars
+    model = nbody_ics.with_bh_binary(nbody_ics.king(n_stars, 7.0, 13), 0.01, 0.2)
+    t_end = int(args.c3_t_end * 2 ** 20)
+    k_min = max(3, int(np.ceil(-np.log2(args.c3_t_end))))
+    log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d)"
+        % (n_stars, t_end / 2.0 ** 20, k_min))
+    x0 = model.x[:, :2].copy()
+    sim, rec = integrate_run(model, "c3", t_end, order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1,
+                             eta_start=0.01, k_min=k_min, k_max=20)
+    h = sim.to_numpy()
+    sep0 = float(np.linalg.norm(x0[:, 0] - x0[:, 1]))
+    sep1 = float(np.linalg.norm(h["x"][:, 0] - h["x"][:, 1]))
+    rec["bh_separation"] = [sep0, sep1]
+    log("[c3] BH separation %.6f -> %.6f" % (sep0, sep1))
+    line = {
+        "metric": "C3: whole-run pair interactions/s, King W0=7 2^20 stars + BH binary, 8th order, MIXED",
+        "value": rec["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1, "steps": rec["steps"],
+        "warmup": 0, "ms_per_step": rec["wall_s"] / max(rec["steps"], 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "King W0=7 %d stars (seed 13) + two 0.01-mass BHs on a circular orbit of separation "
+                               "0.2 (mutually unsoftened), eps = 1e-4, 8th-order Hermite, eta = 0.1, t = 0 -> %.5f"
+                               % (n_stars, t_end / 2.0 ** 20), "n": model.n, "order": 8},
+        "run": rec,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["king1m", "batched", "microbench"], default="king1m")
+    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "c2", "c3"], default="king1m")
+    ap.add_argument("--c2-n", type=int, default=131072)
+    ap.add_argument("--c2-t-end", type=float, default=1.0)
+    ap.add_argument("--c3-stars", type=int, default=1 << 20)
+    ap.add_argument("--c3-t-end", type=float, default=1.0 / 256)
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")
     ap.add_argument("--micro-rows", type=int, default=512, help="microbench: active rows checked against the oracle")
@@ -472,7 +623,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     # default shapes: what nbody_autotune selects for this workload on MI355X
     # (fixed here so that the timed kernel is the profiled one); "" = autotune
-    ap.add_argument("--force-shape-mixed", default="1,64,16,1",
+    ap.add_argument("--force-shape-mixed", default="2,256,16,2",
                     help="ni,block,n_split,jpath of the MIXED force ('' = autotune up to --tune-max)")
     ap.add_argument("--force-shape-fp64", default="2,128,32,1",
                     help="ni,block,n_split,jpath of the FP64 force ('' = autotune up to --tune-max)")
@@ -508,6 +659,12 @@ def main():
         return
     if args.workload == "microbench":
         run_microbench(args)
+        return
+    if args.workload == "c2":
+        run_c2(args)
+        return
+    if args.workload == "c3":
+        run_c3(args)
         return
 
     t0 = time.perf_counter()

@@ -92,9 +92,10 @@ k_force(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *__r
 #pragma unroll
         for (int c = 0; c < 13; ++c) zero_part(p[k][c]);
     for (int64_t jc = js0; jc < j1; jc += CH) {
-        const int64_t je = (jc + CH < j1) ? jc + CH : j1;
+        const int cnt = int(((jc + CH < j1) ? jc + CH : j1) - jc);   // <= n <= 2^26
 #pragma unroll 2
-        for (int64_t j = jc; j < je; ++j) {
+        for (int u = 0; u < cnt; ++u) {
+            const int64_t j = jc + u;
             const Rec rj = rec[j];
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
@@ -124,7 +125,6 @@ k_force_lds(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t 
             double *__restrict__ o_pot, double *__restrict__ part)
 {
     using Rec = typename Pol::Rec;
-    using Part = typename Pol::Part;
     using ET = typename Pol::ET;
     __shared__ Rec tile[2][TILE];
     const ET e2 = ET(eps2);

@@ -320,24 +320,21 @@ __device__ __forceinline__ void lds_tiles(const typename Pol::Rec *__restrict__ 
         }
         const Rec *tr = tile[buf];
         const int cnt = (j1 - jt < TILE) ? int(j1 - jt) : TILE;
-        int jj = 0;
-        while (jj < cnt) {
-            const int seg = (cnt - jj < CH - since) ? cnt - jj : CH - since;
+        // the next record is read from LDS while the current one is used
+        Rec nxt = tr[0];
 #pragma unroll UNROLL
-            for (int u = 0; u < seg; ++u) {
-                const Rec rj = tr[jj + u];
-                const int64_t j = jt + jj + u;
+        for (int u = 0; u < cnt; ++u) {
+            const Rec rj = nxt;
+            nxt = tr[(u + 1 < cnt) ? u + 1 : u];
+            const int64_t j = jt + u;
 #pragma unroll
-                for (int k = 0; k < NI; ++k) {
-                    // the self pair adds nothing to a, jerk, ...; only the
-                    // potential needs it masked
-                    if constexpr (Pol::kWithPot) Pol::template pair<true>(ip[k], rj, e2, j != iidx[k], p[k]);
-                    else Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
-                }
+            for (int k = 0; k < NI; ++k) {
+                // the self pair adds nothing to a, jerk, ...; only the
+                // potential needs it masked
+                if constexpr (Pol::kWithPot) Pol::template pair<true>(ip[k], rj, e2, j != iidx[k], p[k]);
+                else Pol::template pair<false>(ip[k], rj, e2, true, p[k]);
             }
-            jj += seg;
-            since += seg;
-            if (since == CH) {
+            if (++since == CH) {
                 flush<Part, NI>(p, acc);
                 since = 0;
             }
