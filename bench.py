@@ -313,7 +313,8 @@ def run_batched(args):
         del sim
     log("[per-cluster] %d steps over %d contexts: %.1f s, %.4e interactions/s"
         % (tot_steps, len(models), tot_wall, tot_inter / tot_wall))
-    per_cluster = {"interactions_per_s": tot_inter / tot_wall, "seconds": tot_wall, "interactions": tot_inter}
+    per_cluster = {"interactions_per_s": tot_inter / tot_wall, "seconds": tot_wall, "interactions": tot_inter,
+                   "skipped": bool(args.skip_per_cluster)}
     line = {
         "metric": BATCH_METRIC,
         "value": batched["interactions_per_s"],
@@ -336,7 +337,8 @@ def run_batched(args):
         "batched_graph": batched,
         "batched_eager": eager,
         "one_context_per_cluster": per_cluster,
-        "graph_over_per_cluster": batched["interactions_per_s"] / per_cluster["interactions_per_s"],
+        "graph_over_per_cluster": (batched["interactions_per_s"] / per_cluster["interactions_per_s"]
+                                   if per_cluster["interactions_per_s"] > 0 else None),
     }
     print(json.dumps(line), flush=True)
 

@@ -49,7 +49,6 @@ struct BatchLaunch {
     int64_t *tnext;             // [nc]   next block time of each cluster
     int64_t *bmin;              // [nc][nb]
     int32_t *bcnt;              // [nc][nb]
-    int64_t *boff;              // [nc][nb]
     BatchPlan *plan;
     BatchCounters *ctr;
     int32_t *act;               // [n] concatenated active lists

@@ -37,12 +37,14 @@ __device__ __forceinline__ int64_t b_next(const int64_t *t_tick, const int32_t *
 }
 
 // Block b of cluster c covers [off[c] + b*kBBlock, min(off[c] + (b+1)*kBBlock, off[c+1])).
+// Also clears the cluster's active count, which k_b_count accumulates.
 __global__ void __launch_bounds__(kBThreads)
 k_b_min(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-        int nb, int64_t *__restrict__ bmin)
+        int nb, int64_t *__restrict__ bmin, BatchPlan *__restrict__ pl)
 {
     __shared__ int64_t sm[kBThreads];
     const int c = blockIdx.y, b = blockIdx.x;
+    if (b == 0 && threadIdx.x == 0) pl->nact[c] = 0;
     const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
     int64_t mn = INT64_MAX;
     for (int k = 0; k < kBBlock / kBThreads; ++k) {
@@ -61,11 +63,13 @@ k_b_min(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, con
     if (threadIdx.x == 0) bmin[int64_t(c) * nb + b] = sm[0];
 }
 
-// Cluster minimum (from the block minima), then this block's active count.
-// all_active != 0 marks every particle active (initialisation).
+// Cluster minimum (from the block minima), then this block's active count,
+// also added into the cluster's count (integer atomics: the total does not
+// depend on their order).  all_active != 0 marks every particle active
+// (initialisation).
 __global__ void __launch_bounds__(kBThreads)
 k_b_count(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-          int nb, const int64_t *__restrict__ bmin, int all_active, const BatchPlan *__restrict__ pl,
+          int nb, const int64_t *__restrict__ bmin, int all_active, BatchPlan *__restrict__ pl,
           int64_t *__restrict__ tnext, int32_t *__restrict__ bcnt)
 {
     __shared__ int64_t sm[kBThreads];
@@ -99,6 +103,7 @@ k_b_count(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, c
     }
     if (threadIdx.x == 0) {
         bcnt[int64_t(c) * nb + b] = cnt[0];
+        if (cnt[0] > 0) atomicAdd(reinterpret_cast<unsigned long long *>(&pl->nact[c]), (unsigned long long)cnt[0]);
         if (b == 0) tnext[c] = tn;
     }
 }
@@ -126,8 +131,23 @@ __device__ void block_scan(int64_t *v, int n, int64_t *sh)
     __syncthreads();
 }
 
-// The plan of one batched step (one block).  For every cluster: active count
-// and offset, j-splits and work items.  Items are sized by cost: the step's
+// Sum over the block of one value per thread (the result is returned to
+// every thread).
+__device__ int64_t block_sum(int64_t v, int64_t *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kBThreads / 2; st > 0; st >>= 1) {
+        if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    const int64_t r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// The plan of one batched step (one block).  For every cluster: active
+// offset, j-splits and work items.  Items are sized by cost: the step's
 // padded work W = sum_c tiles_c * itile * N_c is cut into about k_items items
 // of W / k_items pair evaluations each (a cluster's j-range is split into s_c
 // pieces of at least 512), so no item is much longer than the average and the
@@ -136,34 +156,23 @@ __device__ void block_scan(int64_t *v, int n, int64_t *sh)
 // s_c <= itile N_c k_items / W + 1, so sum_c s_c a_c <= itile k_items + n.
 // Also resets the work queue and adds the step's interactions to the counters.
 __global__ void __launch_bounds__(kBThreads)
-k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
-         const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int64_t *__restrict__ boff,
+k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ ord, const int64_t *__restrict__ tnext,
          BatchPlan *__restrict__ pl, int ncomp, int k_items, int itile, BatchCounters *__restrict__ ctr)
 {
     __shared__ int64_t sh[kBThreads];
-    // per-cluster active counts and block offsets inside the cluster
-    int64_t w = 0;
+    int64_t w = 0, inter = 0, live = 0;
     for (int c = threadIdx.x; c < nc; c += kBThreads) {
-        int64_t s = 0;
-        for (int b = 0; b < nb; ++b) {
-            boff[int64_t(c) * nb + b] = s;
-            s += bcnt[int64_t(c) * nb + b];
-        }
-        pl->nact[c] = s;
-        pl->aoff[c] = s;
-        if (s > 0) pl->tcur[c] = tnext[c];
-        w += (s + itile - 1) / itile * itile * (off[c + 1] - off[c]);
+        const int64_t a = pl->nact[c], nn = off[c + 1] - off[c];
+        pl->aoff[c] = a;
+        if (a > 0) pl->tcur[c] = tnext[c];
+        w += (a + itile - 1) / itile * itile * nn;
+        inter += a * nn;
+        live += a > 0 ? 1 : 0;
     }
-    // total padded work W (tree sum; integer, so order-free)
-    sh[threadIdx.x] = w;
-    __syncthreads();
-    for (int st = kBThreads / 2; st > 0; st >>= 1) {
-        if (int(threadIdx.x) < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-        __syncthreads();
-    }
-    const int64_t W = sh[0];
+    const int64_t W = block_sum(w, sh);
+    inter = block_sum(inter, sh);
+    live = block_sum(live, sh);
     const int64_t w_item = W / k_items + 1;
-    __syncthreads();
     block_scan(pl->aoff, nc, sh);
     // splits, items (in rank order), partial rows (in cluster order)
     for (int r = threadIdx.x; r < nc; r += kBThreads) {
@@ -184,16 +193,8 @@ k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restr
     __syncthreads();
     block_scan(pl->ioff, nc, sh);
     block_scan(pl->poff, nc, sh);
-    // global block offsets of the active lists
-    for (int c = threadIdx.x; c < nc; c += kBThreads)
-        for (int b = 0; b < nb; ++b) boff[int64_t(c) * nb + b] += pl->aoff[c];
     if (threadIdx.x == 0) {
         pl->queue = 0;
-        int64_t inter = 0, live = 0;
-        for (int c = 0; c < nc; ++c) {
-            inter += pl->nact[c] * (off[c + 1] - off[c]);
-            live += pl->nact[c] > 0 ? 1 : 0;
-        }
         pl->n_live = live;
         ctr->interactions += inter;
         ctr->sum_n_act += pl->aoff[nc];
@@ -201,15 +202,20 @@ k_b_plan(int nc, int nb, const int64_t *__restrict__ off, const int32_t *__restr
     }
 }
 
-// Ordered active lists: block (b, c) writes its actives at boff[c][b].
+// Ordered active lists: block (b, c) writes its actives after those of the
+// cluster's earlier blocks, at aoff[c] + sum of bcnt[c][0 .. b).
 __global__ void __launch_bounds__(kBThreads)
 k_b_compact(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-            int nb, const int64_t *__restrict__ tnext, const int64_t *__restrict__ boff, int all_active,
+            int nb, const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int all_active,
             const BatchPlan *__restrict__ pl, int32_t *__restrict__ act)
 {
     __shared__ int s[kBThreads];
+    __shared__ int64_t sb[kBThreads];
     constexpr int PER = kBBlock / kBThreads;
     const int c = blockIdx.y, b = blockIdx.x;
+    int64_t before = 0;
+    for (int k = threadIdx.x; k < b; k += kBThreads) before += bcnt[int64_t(c) * nb + k];
+    const int64_t block_off = pl->aoff[c] + block_sum(before, sb);
     const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
     const int64_t tn = tnext[c];
     const bool live = pl->nact[c] > 0;
@@ -230,7 +236,7 @@ k_b_compact(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick,
         s[threadIdx.x] += add;
         __syncthreads();
     }
-    int64_t pos = boff[int64_t(c) * nb + b] + s[threadIdx.x] - k0;
+    int64_t pos = block_off + s[threadIdx.x] - k0;
 #pragma unroll
     for (int k = 0; k < PER; ++k)
         if (flags[k]) act[pos++] = int32_t(base + k);
@@ -341,23 +347,24 @@ k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const
            int64_t stride)
 {
     constexpr int NV = 3 * (P / 2);
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t total = pl->aoff[nc];
-    if (t >= total * NV) return;
-    const int cc = int(t / total);
-    const int64_t r = t - int64_t(cc) * total;
-    int lo = 0, hi = nc;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (pl->aoff[mid] <= r) lo = mid; else hi = mid;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total * NV;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int cc = int(t / total);
+        const int64_t r = t - int64_t(cc) * total;
+        int lo = 0, hi = nc;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (pl->aoff[mid] <= r) lo = mid; else hi = mid;
+        }
+        const int64_t na = pl->nact[lo], q = r - pl->aoff[lo];
+        const double *src = part + pl->poff[lo];
+        double s = 0.0;
+        for (int sp = 0; sp < pl->split[lo]; ++sp) s += src[(int64_t(sp) * ncomp + cc) * na + q];
+        double *outs[4] = {o0, o1, o2, o3};
+        double *o = outs[cc / 3];
+        if (o) o[(cc % 3) * stride + r] = s;
     }
-    const int64_t na = pl->nact[lo], q = r - pl->aoff[lo];
-    const double *src = part + pl->poff[lo];
-    double s = 0.0;
-    for (int sp = 0; sp < pl->split[lo]; ++sp) s += src[(int64_t(sp) * ncomp + cc) * na + q];
-    double *outs[4] = {o0, o1, o2, o3};
-    double *o = outs[cc / 3];
-    if (o) o[(cc % 3) * stride + r] = s;
 }
 
 template <int P>
@@ -369,15 +376,16 @@ k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *_
             int32_t *__restrict__ level, const double *__restrict__ force, double eta, int rule, int k_min, int k_max,
             BatchCounters *__restrict__ ctr)
 {
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= pl->aoff[nc]) return;
-    const int64_t i = act[r];
-    if (i < 0 || i >= n) return;
+    const int64_t total = pl->aoff[nc];
     double *dst[6] = {d0, d1, d2, d3, d4, d5};
     const double *fnew[4] = {force, force + 3 * n, force + 6 * n, force + 9 * n};
-    const int fl = correct_one<P>(n, i, tnext[cid[i]], fnew, n, r, x, v, dst, t_tick, level, eta, rule, k_min, k_max);
-    if (fl & 2) atomicAdd(&ctr->underflow, 1ull);
-    if (fl & 1) atomicAdd(&ctr->nonfinite, 1ull);
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < total; r += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = act[r];
+        if (i < 0 || i >= n) continue;
+        const int fl = correct_one<P>(n, i, tnext[cid[i]], fnew, n, r, x, v, dst, t_tick, level, eta, rule, k_min, k_max);
+        if (fl & 2) atomicAdd(&ctr->underflow, 1ull);
+        if (fl & 1) atomicAdd(&ctr->nonfinite, 1ull);
+    }
 }
 
 __global__ void k_b_requeue(BatchPlan *__restrict__ pl)
@@ -386,6 +394,11 @@ __global__ void k_b_requeue(BatchPlan *__restrict__ pl)
 }
 
 unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+// Workgroups of the grid-stride kernels whose work is bounded by the step's
+// active count (at most n rows): enough to fill the chip, few enough that a
+// step with a small active set does not pay for launching idle workgroups.
+constexpr unsigned kStrideGrid = 2048;
 
 template <class Pol, int P>
 hipError_t force_p(const BatchLaunch &L, const void *rec, hipStream_t s)
@@ -412,7 +425,8 @@ hipError_t force_prec(int precision, const BatchLaunch &L, const void *rec, hipS
 template <int P>
 hipError_t reduce_p(const BatchLaunch &L, double *o0, double *o1, double *o2, double *o3, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_b_reduce<P>), dim3(nblk(L.n * 3 * (P / 2), 256)), dim3(256), 0, s, L.nc, L.n, L.plan,
+    const unsigned g = nblk(L.n * 3 * (P / 2), 256);
+    hipLaunchKernelGGL((k_b_reduce<P>), dim3(g < kStrideGrid ? g : kStrideGrid), dim3(256), 0, s, L.nc, L.n, L.plan,
                        3 * (P / 2), L.part, o0, o1, o2, o3, L.n);
     return hipGetLastError();
 }
@@ -461,12 +475,12 @@ hipError_t batch_cid(const BatchLaunch &L, hipStream_t s)
 hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_active, int order, hipStream_t s)
 {
     const dim3 g(unsigned(L.nb), unsigned(L.nc), 1u);
-    hipLaunchKernelGGL(k_b_min, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin);
+    hipLaunchKernelGGL(k_b_min, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, L.plan);
     hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, all_active,
                        L.plan, L.tnext, L.bcnt);
-    hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.nb, L.off, L.ord, L.tnext, L.bcnt, L.boff,
-                       L.plan, 3 * (order / 2), L.k_items, L.itile, L.ctr);
-    hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.boff,
+    hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.off, L.ord, L.tnext, L.plan,
+                       3 * (order / 2), L.k_items, L.itile, L.ctr);
+    hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.bcnt,
                        all_active, L.plan, L.act);
     return hipGetLastError();
 }
@@ -506,7 +520,8 @@ hipError_t batch_reduce(const BatchLaunch &L, int order, double *o0, double *o1,
 
 hipError_t batch_correct(const BatchLaunch &L, const nbody_config &c, const nbody_state &st, hipStream_t s)
 {
-    const unsigned g = nblk(L.n, 256);
+    const unsigned g0 = nblk(L.n, 256);
+    const unsigned g = g0 < kStrideGrid ? g0 : kStrideGrid;
 #define NB_BC(P)                                                                                              \
     hipLaunchKernelGGL((k_b_correct<P>), dim3(g), dim3(256), 0, s, L.n, L.nc, L.act, L.cid, L.tnext, L.plan,     \
                        st.x, st.v, st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5], st.t_tick, st.level,    \

@@ -17,7 +17,7 @@ using nb::fail;
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BatchLayout {
-    size_t off, ord, cid, tnext, bmin, bcnt, boff, plan, nact, aoff, ioff, poff, jchunk, split, tcur, ctr, act,
+    size_t off, ord, cid, tnext, bmin, bcnt, plan, nact, aoff, ioff, poff, jchunk, split, tcur, ctr, act,
         part, force, rec, energy, total;
 };
 
@@ -51,7 +51,6 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.tnext = take(nc * sizeof(int64_t));
     L.bmin = take(cells * sizeof(int64_t));
     L.bcnt = take(cells * sizeof(int32_t));
-    L.boff = take(cells * sizeof(int64_t));
     L.plan = take(sizeof(nb::BatchPlan));
     L.nact = take(nc * sizeof(int64_t));
     L.aoff = take((nc + 1) * sizeof(int64_t));
@@ -219,7 +218,6 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.tnext = at<int64_t>(b, lay.tnext);
     L.bmin = at<int64_t>(b, lay.bmin);
     L.bcnt = at<int32_t>(b, lay.bcnt);
-    L.boff = at<int64_t>(b, lay.boff);
     L.plan = at<nb::BatchPlan>(b, lay.plan);
     L.ctr = at<nb::BatchCounters>(b, lay.ctr);
     L.act = at<int32_t>(b, lay.act);
