@@ -455,7 +455,7 @@ def run_microbench(args):
     print(json.dumps(line), flush=True)
 
 
-def integrate_run(model, label, t_end_tick, **kw):
+def integrate_run(model, label, t_end_tick, hist_pass=True, **kw):
     """Integrate a Simulation to t_end_tick with nbody_step; returns the run
     record (steps, interactions/s, N_act histogram, energies, phase times)."""
     import torch
@@ -465,42 +465,49 @@ def integrate_run(model, label, t_end_tick, **kw):
     E0 = sum(sim.energy())
     sim.predict(0)
     sim.autotune(min(65536, model.n), 2)
-    sim.set_timing(True)
     torch.cuda.synchronize()
     hist = np.zeros(32)
     whist = np.zeros(32)
-    steps, n_act_sum = 0, 0
+    # nbody_run in slices of 1/64 time unit (progress lines), then one pass with
+    # nbody_step per step for the active-block histogram, which needs each n_act
+    steps = 0
     t0 = time.perf_counter()
-    last = t0
-    while True:
-        nxt = int((sim.t_tick + (torch.ones_like(sim.t_tick) << (20 - sim.level.to(torch.int64)))).min())
-        if nxt > t_end_tick:
-            break
-        t, na = sim.step()
-        steps += 1
-        n_act_sum += na
-        b = int(np.log2(na))
-        hist[b] += 1
-        whist[b] += float(na) * model.n
-        if time.perf_counter() - last > 20.0:
-            last = time.perf_counter()
-            log("[%s] t = %.5f, %d steps" % (label, t / 2.0 ** 20, steps))
+    t_cur = 0
+    while t_cur < t_end_tick:
+        t_slice = min(t_end_tick, t_cur + (1 << 14))
+        k, _ = sim.run(t_slice)
+        steps += k
+        t_cur = t_slice
+        log("[%s] t = %.5f, %d steps" % (label, t_cur / 2.0 ** 20, steps))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    n_act_sum = sim.stats().sum_n_act
+    if hist_pass:
+        h_sim = Simulation(model.m, model.x, model.v, **kw)
+        h_sim.init()
+        while True:
+            before = h_sim.stats().sum_n_act
+            k, _ = h_sim.run(t_end_tick, 1)
+            if k == 0:
+                break
+            na = h_sim.stats().sum_n_act - before
+            b = int(np.log2(na))
+            hist[b] += 1
+            whist[b] += float(na) * model.n
+        h_sim.close()
     E1 = sum(sim.energy())
     st = sim.stats()
-    phases, nt = sim.timers()
     rec = {"steps": steps, "wall_s": wall, "interactions": st.interactions,
            "interactions_per_s": st.interactions / wall, "mean_n_act": n_act_sum / max(steps, 1),
            "dE_over_E": (E1 - E0) / E0, "dt_rule": sim.dt_rule, "dt_underflow": st.dt_underflow,
-           "phase_ms_total": phases,
            "n_act_hist_log2": {"bins": [int(2 ** b) for b in range(32) if hist[b] > 0],
                                "steps": [int(hist[b]) for b in range(32) if hist[b] > 0],
                                "interaction_share": [float(whist[b] / whist.sum()) for b in range(32) if hist[b] > 0]}}
+    if not hist_pass:
+        rec.pop("n_act_hist_log2")
     log("[%s] %d steps to t = %.4f in %.1f s: %.4e interactions/s (whole steps), mean n_act %.0f, |dE/E| %.3e, "
-        "rule %d, phases (s) %s" % (label, steps, t_end_tick / 2.0 ** 20, wall, rec["interactions_per_s"],
-                                    rec["mean_n_act"], abs(rec["dE_over_E"]), sim.dt_rule,
-                                    {k: round(v / 1e3, 2) for k, v in phases.items()}))
+        "rule %d" % (label, steps, t_end_tick / 2.0 ** 20, wall, rec["interactions_per_s"], rec["mean_n_act"],
+                     abs(rec["dE_over_E"]), sim.dt_rule))
     return sim, rec
 
 
@@ -549,7 +556,8 @@ def run_c2(args):
     kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
     runs = {}
     for label, prec, rule in (("mixed", "mixed", 0), ("fp64_rule_order4", "fp64", 2), ("fp64", "fp64", 0)):
-        sim, runs[label] = integrate_run(model, label, t_end, precision=prec, dt_rule=rule, **kw)
+        sim, runs[label] = integrate_run(model, label, t_end, hist_pass=(label == "mixed"), precision=prec,
+                                         dt_rule=rule, **kw)
         sim.close()
         del sim
     runs["mixed_one_cluster_graph"] = integrate_batched_one(model, t_end, kw)
@@ -577,7 +585,7 @@ def run_c3(args):
     log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d)"
         % (n_stars, t_end / 2.0 ** 20, k_min))
     x0 = model.x[:, :2].copy()
-    sim, rec = integrate_run(model, "c3", t_end, order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1,
+    sim, rec = integrate_run(model, "c3", t_end, hist_pass=False, order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1,
                              eta_start=0.01, k_min=k_min, k_max=20)
     h = sim.to_numpy()
     sep0 = float(np.linalg.norm(x0[:, 0] - x0[:, 1]))

@@ -162,6 +162,16 @@ nbody_status nbody_schedule(nbody_ctx *ctx, const nbody_state *state, int32_t *a
  * corrected value became NaN or infinite. */
 nbody_status nbody_step(nbody_ctx *ctx, nbody_state *state, int64_t *t_tick_out, int64_t *n_act_out);
 
+/* Block steps (as nbody_step) until the next block time would exceed
+ * t_end_tick, or max_steps steps: *steps_out (host) = steps taken,
+ * *t_tick_out (host) = time of the last step (0 if none); both may be NULL.
+ * The corrector's counters are read with the next step's scheduler result,
+ * so a run costs one host round trip per step.  Returns NBODY_E_NONFINITE
+ * (after the step that produced it, or the one after) when a corrected value
+ * became NaN or infinite. */
+nbody_status nbody_run(nbody_ctx *ctx, nbody_state *state, int64_t t_end_tick, int64_t max_steps,
+                       int64_t *steps_out, int64_t *t_tick_out);
+
 /* FP64 energy of the state (meaningful when all particles share one time):
  * *ekin = sum m v^2 / 2, *epot = - sum_{i<j} m_i m_j / sqrt(r^2 + eps_ij^2).
  * Host outputs; fixed summation order. */

@@ -38,7 +38,7 @@ def effective_dt_rule(order: int, precision: int, dt_rule: int = 0) -> int:
 #: every symbol the header declares
 EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
-    "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_energy",
+    "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
     "nbody_autotune", "nbody_get_tuning",
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
@@ -93,6 +93,7 @@ def lib():
             "nbody_correct": [P, C.POINTER(nbody_state), I64, P, I64, P, P, P, P],
             "nbody_schedule": [P, C.POINTER(nbody_state), P, C.POINTER(I64), C.POINTER(I64)],
             "nbody_step": [P, C.POINTER(nbody_state), C.POINTER(I64), C.POINTER(I64)],
+            "nbody_run": [P, C.POINTER(nbody_state), I64, I64, C.POINTER(I64), C.POINTER(I64)],
             "nbody_energy": [P, C.POINTER(nbody_state), C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "nbody_get_predicted": [P, P, P, P, P],
             "nbody_get_stats": [P, C.POINTER(nbody_stats)],
@@ -193,6 +194,16 @@ def nbody_step(ctx: int, st: nbody_state):
     na = C.c_int64(0)
     _check(lib().nbody_step(C.c_void_p(ctx), C.byref(st), C.byref(t), C.byref(na)), "nbody_step")
     return int(t.value), int(na.value)
+
+
+def nbody_run(ctx: int, st: nbody_state, t_end_tick: int, max_steps: int = (1 << 62)):
+    """Block steps until the next would pass t_end_tick; returns (steps, t_tick).
+    Raises NBodyError (status NBODY_E_NONFINITE) on a non-finite value."""
+    n = C.c_int64(0)
+    t = C.c_int64(0)
+    _check(lib().nbody_run(C.c_void_p(ctx), C.byref(st), int(t_end_tick), int(max_steps), C.byref(n), C.byref(t)),
+           "nbody_run")
+    return int(n.value), int(t.value)
 
 
 def nbody_energy(ctx: int, st: nbody_state):

@@ -432,25 +432,46 @@ nbody_status nbody_schedule(nbody_ctx *ctx, const nbody_state *st, int32_t *act_
     return NBODY_OK;
 }
 
-nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int64_t *t_tick_out, int64_t *n_act_out)
+}  // extern "C"
+
+namespace {
+
+// Record the device counters read in h; NBODY_E_NONFINITE when the number of
+// non-finite corrected values grew since the last read.
+nbody_status take_counters(nbody_ctx *ctx, const nb::DevScalars &h, int64_t t_tick)
 {
-    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
-    nbody_status s = check_state(ctx, st);
-    if (s != NBODY_OK) return s;
+    const int64_t nonfinite_before = ctx->stats.nonfinite;
+    ctx->stats.dt_underflow = int64_t(h.underflow);
+    ctx->stats.nonfinite = int64_t(h.nonfinite);
+    if (ctx->stats.nonfinite > nonfinite_before)
+        return fail(NBODY_E_NONFINITE, "%lld corrected particles became non-finite at tick %lld",
+                    (long long)(ctx->stats.nonfinite - nonfinite_before), (long long)t_tick);
+    return NBODY_OK;
+}
+
+// One block step unless its time would exceed t_limit (*stepped = false then,
+// and nothing but the scheduler ran).  The scheduler's result is read back to
+// size the force launch; with `check` the counters are read again after the
+// corrector (else the next call's first read sees them).
+nbody_status step_impl(nbody_ctx *ctx, nbody_state *st, int64_t t_limit, bool check, int64_t *t_out,
+                       int64_t *n_act_out, bool *stepped, int64_t *t_prev)
+{
     const nbody_config &c = ctx->cfg;
     int32_t *act = ws_at<int32_t>(ctx, ctx->lay.act);
-    int64_t t_next = 0, n_act = 0;
     const bool tm = ctx->timing && ctx->ev_made;
+    *stepped = false;
     if (tm) NB_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
     NB_HIP(nb::launch_schedule(c.n, st->t_tick, st->level, ctx->ws + ctx->lay.sched, act, scalars(ctx),
                                ctx->stream));
     if (tm) NB_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
     nb::DevScalars h;
-    s = read_scalars(ctx, &h);
+    nbody_status s = read_scalars(ctx, &h);
     if (s != NBODY_OK) return s;
-    t_next = h.t_next;
-    n_act = h.n_act;
+    s = take_counters(ctx, h, *t_prev);   // the previous corrector's counters
+    if (s != NBODY_OK) return s;
+    const int64_t t_next = h.t_next, n_act = h.n_act;
     if (n_act <= 0 || n_act > c.n) return fail(NBODY_E_STATE, "scheduler found %lld active particles", (long long)n_act);
+    if (t_next > t_limit) return NBODY_OK;
     if (tm) NB_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
     s = nbody_predict(ctx, st, t_next);
     if (s != NBODY_OK) return s;
@@ -466,9 +487,12 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int64_t *t_tick_out, in
     if (tm) NB_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
     ctx->stats.steps += 1;
     ctx->stats.sum_n_act += n_act;
-    s = read_scalars(ctx, &h);
-    if (s != NBODY_OK) return s;
+    *stepped = true;
+    *t_out = t_next;
+    *n_act_out = n_act;
+    *t_prev = t_next;
     if (tm) {
+        NB_HIP(hipEventSynchronize(ctx->ev[5]));
         for (int k = 0; k < 5; ++k) {
             float ms = 0.0f;
             NB_HIP(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
@@ -476,15 +500,54 @@ nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int64_t *t_tick_out, in
         }
         ctx->timed_steps += 1;
     }
-    const int64_t nonfinite_before = ctx->stats.nonfinite;
-    ctx->stats.dt_underflow = int64_t(h.underflow);
-    ctx->stats.nonfinite = int64_t(h.nonfinite);
-    if (t_tick_out) *t_tick_out = t_next;
-    if (n_act_out) *n_act_out = n_act;
-    if (ctx->stats.nonfinite > nonfinite_before)
-        return fail(NBODY_E_NONFINITE, "%lld corrected particles became non-finite at tick %lld",
-                    (long long)(ctx->stats.nonfinite - nonfinite_before), (long long)t_next);
+    if (check) {
+        s = read_scalars(ctx, &h);
+        if (s != NBODY_OK) return s;
+        return take_counters(ctx, h, t_next);
+    }
     return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nbody_status nbody_step(nbody_ctx *ctx, nbody_state *st, int64_t *t_tick_out, int64_t *n_act_out)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    int64_t t = 0, na = 0, prev = 0;
+    bool stepped = false;
+    s = step_impl(ctx, st, INT64_MAX, true, &t, &na, &stepped, &prev);
+    if (s != NBODY_OK) return s;
+    if (t_tick_out) *t_tick_out = t;
+    if (n_act_out) *n_act_out = na;
+    return NBODY_OK;
+}
+
+nbody_status nbody_run(nbody_ctx *ctx, nbody_state *st, int64_t t_end_tick, int64_t max_steps, int64_t *steps_out,
+                       int64_t *t_tick_out)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (t_end_tick < 0 || max_steps < 0) return fail(NBODY_E_INVALID, "t_end_tick and max_steps must be >= 0");
+    int64_t steps = 0, t = 0, na = 0, prev = 0;
+    bool stepped = true;
+    while (steps < max_steps) {
+        s = step_impl(ctx, st, t_end_tick, false, &t, &na, &stepped, &prev);
+        if (s != NBODY_OK || !stepped) break;
+        ++steps;
+    }
+    if (s == NBODY_OK && stepped) {   // the last corrector's counters were not read yet
+        nb::DevScalars h;
+        s = read_scalars(ctx, &h);
+        if (s == NBODY_OK) s = take_counters(ctx, h, prev);
+    }
+    if (steps_out) *steps_out = steps;
+    if (t_tick_out) *t_tick_out = prev;
+    return s;
 }
 
 nbody_status nbody_energy(nbody_ctx *ctx, const nbody_state *st, double *ekin, double *epot)

@@ -132,15 +132,14 @@ class Simulation:
     def stats(self) -> abi.nbody_stats:
         return abi.nbody_get_stats(self.ctx)
 
+    def run(self, t_end_tick: int, max_steps: int = 1 << 62):
+        """nbody_run: (steps, time of the last step)."""
+        return abi.nbody_run(self.ctx, self.state, t_end_tick, max_steps)
+
     def integrate(self, t_end_tick: int, max_steps: int = 1 << 62):
-        """Block steps until every particle reaches t_end_tick."""
-        steps = 0
-        while steps < max_steps:
-            nxt = self.t_tick + (torch.ones_like(self.t_tick) << (20 - self.level.to(torch.int64)))
-            if int(nxt.min()) > t_end_tick:
-                break
-            self.step()
-            steps += 1
+        """Block steps until the next one would pass t_end_tick (nbody_run);
+        returns the number of steps."""
+        steps, _ = abi.nbody_run(self.ctx, self.state, t_end_tick, max_steps)
         return steps
 
     def to_numpy(self) -> dict:

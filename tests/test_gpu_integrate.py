@@ -250,3 +250,44 @@ def test_nonfinite_is_reported():
         for _ in range(200):
             sim.step()
     assert e.value.status == abi.NBODY_E_NONFINITE
+
+
+def test_run_equals_single_steps():
+    """nbody_run to t_end takes exactly the steps nbody_step takes one by one
+    (the same kernels and launch shapes: identical bits) and stops before the
+    first block time past t_end."""
+    model = nbody_ics.plummer(700, 91)
+    a = _sim(model, 6, precision="mixed", eta=0.1)
+    b = _sim(model, 6, precision="mixed", eta=0.1)
+    a.init()
+    b.init()
+    t_end = TICKS // 64 + 3 * (TICKS >> 16)
+    steps_a, t_a = a.run(t_end)
+    steps_b, t_b = 0, 0
+    while True:
+        h = b.to_numpy()
+        nxt = int((h["t_tick"] + (1 << (20 - h["level"].astype(np.int64)))).min())
+        if nxt > t_end:
+            break
+        t_b, _ = b.step()
+        steps_b += 1
+    say("run: %d steps to tick %d; single steps %d to tick %d" % (steps_a, t_a, steps_b, t_b))
+    assert (steps_a, t_a) == (steps_b, t_b) and steps_a > 10
+    ha, hb = a.to_numpy(), b.to_numpy()
+    for key in ("x", "v", "t_tick", "level"):
+        np.testing.assert_array_equal(ha[key], hb[key])
+    assert a.stats().steps == b.stats().steps
+    assert a.run(t_end) == (0, 0)
+
+
+def test_run_reports_nonfinite():
+    from paper_1312_1789_amd import abi
+    model = nbody_ics.plummer(512, 92)
+    sim = _sim(model, 4)
+    sim.init()
+    h = sim.to_numpy()
+    h["v"][1, 7] = np.inf
+    sim.load_state(h["x"], h["v"], h["d"], h["t_tick"], h["level"])
+    with pytest.raises(abi.NBodyError) as e:
+        sim.run(TICKS)
+    assert e.value.status == abi.NBODY_E_NONFINITE
