@@ -191,9 +191,12 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
  * block = threads per workgroup (64, 128 or 256), n_split = j-range splits
  * (0 = chosen per call from n_act), jpath = how j records reach the lanes
  * (0 = default for the precision, 1 = wave-uniform scalar loads, 2 = LDS
- * tiles).  A shape set here is used for every later force call (it replaces
- * an autotuned table).  Without either, a call uses ni = 1, the narrowest
- * workgroup of 64, 128 or 256 lanes that holds n_act, and the default split.
+ * tiles, 3 = wave j-split for small active sets: 1, 4 or 16 active rows per
+ * 64-lane workgroup, each row's j range spread over 64, 16 or 4 lanes and
+ * folded across them; ni and block are ignored).  A shape set here is used for every later force call (it replaces
+ * an autotuned table).  Without either, a call uses the wave j-split kernel
+ * for n_act <= 32, else ni = 1, the narrowest workgroup of 64, 128 or 256
+ * lanes that holds n_act, and the default split.
  * Results do not depend on ni, block or jpath; they depend on n_split only
  * through the FP64 summation order (and, in MIXED mode, where the FP32 chunks
  * start). */
@@ -202,8 +205,9 @@ nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t
 /* Autotuner of the force launch (i-tile, j-tile path and j-split per active
  * size): for n_act = 1, 2, 4, ... up to min(max_n_act, n) (at most 31 sizes,
  * and min(max_n_act, n) itself), times `reps` launches of every shape
- * ni in {1, 2} x block in {64, 128, 256} x jpath in {1, 2} x n_split in
- * {s/2, s, 2s} (s = the default split) with HIP events, on the records of the
+ * ni in {1, 2} x block in {64, 128, 256} x jpath in {1, 2} (and jpath 3 for
+ * n_act <= 64) x n_split in {s/2, s, 2s} (s = the default split) with HIP
+ * events, on the records of the
  * last nbody_predict and the first n_act particles, and keeps the fastest.
  * Later force calls use the row of the smallest tuned n_act >= their n_act
  * (the largest row above the table).  Overwrites the context's force scratch;

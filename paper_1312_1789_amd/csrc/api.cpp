@@ -85,11 +85,13 @@ nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec
         a.n_split = ctx->tune[r].n_split;
         a.jpath = ctx->tune[r].jpath;
     } else {
-        // untuned default: workgroups no wider than the active set needs
+        // untuned default: the wave j-split kernel for active sets of up to 32
+        // (the autotuner's choice there on MI355X in every precision), else
+        // workgroups no wider than the active set needs
         a.ni = 1;
         a.block = n_act <= 64 ? 64 : (n_act <= 128 ? 128 : 256);
         a.n_split = 0;
-        a.jpath = 0;
+        a.jpath = n_act <= 32 ? 3 : 0;
     }
     int used = 0;
     NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
@@ -230,7 +232,8 @@ nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5], int64_t *steps)
 nbody_status nbody_set_launch(nbody_ctx *ctx, int32_t ni, int32_t block, int32_t n_split, int32_t jpath)
 {
     if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
-    if (jpath < 0 || jpath > 2) return fail(NBODY_E_INVALID, "jpath must be 0 (auto), 1 (scalar) or 2 (LDS)");
+    if (jpath < 0 || jpath > 3)
+        return fail(NBODY_E_INVALID, "jpath must be 0 (auto), 1 (scalar), 2 (LDS) or 3 (wave j-split)");
     if (ni != 1 && ni != 2) return fail(NBODY_E_INVALID, "ni must be 1 or 2");
     if (block != 64 && block != 128 && block != 256) return fail(NBODY_E_INVALID, "block must be 64, 128 or 256");
     if (n_split < 0 || n_split > 65535) return fail(NBODY_E_INVALID, "n_split must be in [0, 65535]");
@@ -269,8 +272,10 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int64_t max_n_act, int32_t reps)
         nb::TuneRow best{na, 1, 256, 0, 0, 1e300};
         for (int ni : {1, 2})
             for (int block : {64, 128, 256})
-                for (int jpath : {1, 2}) {
-                    const int base = nb::auto_split(n, na, ni, block);
+                for (int jpath : {1, 2, 3}) {
+                    // the wave j-split kernel ignores ni and block, and serves small active sets
+                    if (jpath == 3 && (ni != 1 || block != 64 || na > 64)) continue;
+                    const int base = nb::auto_split_path(n, na, ni, block, jpath);
                     int prev = -1;
                     for (int mult : {1, 2, 4}) {   // splits base / 2, base, base * 2
                         int sp = mult == 1 ? base / 2 : (mult == 2 ? base : base * 2);

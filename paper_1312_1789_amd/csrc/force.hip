@@ -145,6 +145,83 @@ k_force_lds(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t 
                            o_pot, part);
 }
 
+// Kernel C (wave j-split, for active sets smaller than a wavefront): a
+// 64-lane workgroup holds R active rows, each on JS = 64 / R lanes; lane s of
+// a row takes j = j0 + s, j0 + s + JS, ... of the split's range, with vector
+// loads (the JS lanes of a row read consecutive records; the rows share
+// them).  The row's JS partial sums are then folded with a fixed cross-lane
+// butterfly, so a workgroup's serial work is 1/JS of kernels A and B and the
+// result is the same for every run.  Hard pairs (both indices below n_hard)
+// and the self pair are handled per pair.
+template <class Pol, int P, int R>
+__global__ void __launch_bounds__(64)
+k_force_ws(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *__restrict__ act, int64_t n_act,
+           double eps2, int64_t n_hard, int64_t j_chunk, int n_split, double *__restrict__ o_acc,
+           double *__restrict__ o_jrk, double *__restrict__ o_snp, double *__restrict__ o_crk,
+           double *__restrict__ o_pot, double *__restrict__ part)
+{
+    using Rec = typename Pol::Rec;
+    using Part = typename Pol::Part;
+    using ET = typename Pol::ET;
+    constexpr int JS = 64 / R;
+    constexpr int NV = 3 * (P / 2);
+    const ET e2 = ET(eps2);
+    const int lane = int(threadIdx.x);
+    const int r = lane / JS, sl = lane % JS;
+    const int64_t q = int64_t(blockIdx.x) * R + r;
+    const int split = blockIdx.y;
+    const int64_t j0 = int64_t(split) * j_chunk;
+    const int64_t j1 = (j0 + j_chunk < n) ? j0 + j_chunk : n;
+    const int64_t qq = q < n_act ? q : n_act - 1;   // padding rows recompute the last row; never stored
+    const int64_t ia = act[qq];
+    const int64_t i = (ia >= 0 && ia < n) ? ia : 0;
+    const typename Pol::I ip = Pol::load(rec[i]);
+    const bool i_hard = i < n_hard;
+    double acc[13];
+    Part p[13];
+#pragma unroll
+    for (int c = 0; c < 13; ++c) {
+        acc[c] = 0.0;
+        zero_part(p[c]);
+    }
+    constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk : (1 << 30);
+    int since = 0;
+    int64_t j = j0 + sl;
+    Rec nxt = rec[j < j1 ? j : j1 - 1];
+    for (; j < j1; j += JS) {
+        const Rec rj = nxt;
+        nxt = rec[j + JS < j1 ? j + JS : j1 - 1];
+        const ET el = (i_hard && j < n_hard) ? ET(0) : e2;
+        Pol::template pair<true>(ip, rj, el, j != i, p);
+        if (++since == CH) {
+            flush<Part, 1>(&p, &acc);
+            since = 0;
+        }
+    }
+    flush<Part, 1>(&p, &acc);
+    // fold the JS lanes of the row (lanes r*JS .. r*JS + JS - 1)
+#pragma unroll
+    for (int m = JS / 2; m > 0; m >>= 1)
+#pragma unroll
+        for (int c = 0; c < 13; ++c) acc[c] += __shfl_xor(acc[c], m, 64);
+    if (sl != 0 || q >= n_act) return;
+    if (n_split == 1) {
+        double *outs[4] = {o_acc, o_jrk, o_snp, o_crk};
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double *o = outs[c / 3];
+            if (o) o[(c % 3) * n_act + q] = acc[c];
+        }
+        if (Pol::kWithPot && o_pot) o_pot[q] = -acc[kPot];
+    } else {
+        constexpr int NC = NV + 1;
+        double *base = part + int64_t(split) * NC * n_act;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) base[int64_t(c) * n_act + q] = acc[c];
+        if (Pol::kWithPot) base[int64_t(NV) * n_act + q] = -acc[kPot];
+    }
+}
+
 // Sum of the j-split partial results.  A group of L lanes (L = 1, 4, 16 or
 // 64, consecutive lanes of one wavefront) owns one output value: lane l adds
 // splits l, l + L, l + 2L, ... in order, then the group folds its L sums with
@@ -210,7 +287,14 @@ hipError_t run(const ForceArgs &a, hipStream_t s, const Shape &sh)
     const auto *rec = static_cast<const typename Pol::Rec *>(a.rec);
 #define NB_FORCE_ARGS rec, a.n, a.act, a.n_act, a.eps2, a.n_hard, sh.j_chunk, sh.n_split, a.out[0], a.out[1], \
                       a.out[2], a.out[3], a.out[4], a.part
-    if (sh.jpath == 1) {
+    if (sh.jpath == 3) {
+        // rows per wave for the active set: 1, 4 or 16
+        const int rw = a.n_act <= 1 ? 1 : (a.n_act <= 4 ? 4 : 16);
+        const dim3 g3{unsigned((a.n_act + rw - 1) / rw), unsigned(sh.n_split), 1u};
+        if (rw == 1) hipLaunchKernelGGL((k_force_ws<Pol, P, 1>), g3, dim3(64), 0, s, NB_FORCE_ARGS);
+        else if (rw == 4) hipLaunchKernelGGL((k_force_ws<Pol, P, 4>), g3, dim3(64), 0, s, NB_FORCE_ARGS);
+        else hipLaunchKernelGGL((k_force_ws<Pol, P, 16>), g3, dim3(64), 0, s, NB_FORCE_ARGS);
+    } else if (sh.jpath == 1) {
         hipLaunchKernelGGL((k_force<Pol, P, NI>), grid, dim3(sh.block), 0, s, NB_FORCE_ARGS);
     } else if (sh.block == 64) {
         hipLaunchKernelGGL((k_force_lds<Pol, P, NI, 64, 2, 64>), grid, dim3(64), 0, s, NB_FORCE_ARGS);
@@ -228,7 +312,7 @@ hipError_t run(const ForceArgs &a, hipStream_t s, const Shape &sh)
 template <class Pol, int P>
 hipError_t run_ni(const ForceArgs &a, hipStream_t s, const Shape &sh)
 {
-    if (sh.ni == 2) return run<Pol, P, 2>(a, s, sh);
+    if (sh.ni == 2 && sh.jpath != 3) return run<Pol, P, 2>(a, s, sh);
     return run<Pol, P, 1>(a, s, sh);
 }
 
@@ -267,7 +351,22 @@ int auto_split(int64_t n, int64_t n_act, int ni, int block)
     const int64_t waves = tiles * (block / 64);
     const int64_t target_waves = 256 * 4 * 8;   // CUs x SIMDs x waves per SIMD
     int64_t sp = (target_waves + waves - 1) / waves;
-    const int64_t max_by_n = n / 256 > 0 ? n / 256 : 1;
+    const int64_t max_by_n = n / kMixedChunk > 0 ? n / kMixedChunk : 1;   // splits of at least one FP32 chunk
+    const int64_t max_by_part = kPartEntries / (n_act > 0 ? n_act : 1);
+    if (sp > max_by_n) sp = max_by_n;
+    if (sp > max_by_part) sp = max_by_part;
+    if (sp > 65535) sp = 65535;
+    return sp < 1 ? 1 : int(sp);
+}
+
+int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath)
+{
+    if (jpath != 3) return auto_split(n, n_act, ni, block);
+    // kernel C: one wave per 1, 4 or 16 rows; splits for about 8 waves per SIMD
+    const int64_t rw = n_act <= 1 ? 1 : (n_act <= 4 ? 4 : 16);
+    const int64_t waves = (n_act + rw - 1) / rw;
+    int64_t sp = (256 * 4 * 8 + waves - 1) / waves;
+    const int64_t max_by_n = n / kMixedChunk > 0 ? n / kMixedChunk : 1;
     const int64_t max_by_part = kPartEntries / (n_act > 0 ? n_act : 1);
     if (sp > max_by_n) sp = max_by_n;
     if (sp > max_by_part) sp = max_by_part;
@@ -281,8 +380,8 @@ hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_
     sh.ni = (a.ni == 2) ? 2 : 1;
     sh.block = (a.block == 64 || a.block == 128) ? a.block : 256;
     // j path: FP64 reads j records from SGPRs, the FP32 modes from LDS
-    sh.jpath = a.jpath == 1 || a.jpath == 2 ? a.jpath : (precision == NBODY_FP64 ? 1 : 2);
-    int sp = a.n_split > 0 ? a.n_split : auto_split(a.n, a.n_act, sh.ni, sh.block);
+    sh.jpath = a.jpath >= 1 && a.jpath <= 3 ? a.jpath : (precision == NBODY_FP64 ? 1 : 2);
+    int sp = a.n_split > 0 ? a.n_split : auto_split_path(a.n, a.n_act, sh.ni, sh.block, sh.jpath);
     if (int64_t(sp) * a.n_act > kPartEntries) sp = int(kPartEntries / a.n_act);
     if (sp < 1) sp = 1;
     // split length: a multiple of the MIXED chunk so chunks never straddle splits

@@ -92,6 +92,9 @@ hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_
 // j-splits that give about 8 waves per SIMD for n_act rows in workgroups of
 // `block` lanes with ni rows per lane (the default when n_split is 0).
 int auto_split(int64_t n, int64_t n_act, int ni, int block);
+// The default split of a j path (jpath 3, the wave j-split kernel, sizes its
+// own workgroups: 1, 4 or 16 active rows in 64 lanes).
+int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath);
 
 // One row of the force-launch table filled by nbody_autotune.
 struct TuneRow {

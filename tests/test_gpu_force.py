@@ -126,7 +126,7 @@ def test_autotuned_launch_keeps_parity(small_case, precision):
     say("tuned table (%s): %s" % (precision, [(r[0], r[1], r[2], r[3], r[4], round(r[5], 4)) for r in table]))
     assert [r[0] for r in table] == [1 << k for k in range(11)]
     for na, ni, block, sp, jpath, ms in table:
-        assert ni in (1, 2) and block in (64, 128, 256) and jpath in (1, 2) and sp >= 1 and ms > 0
+        assert ni in (1, 2) and block in (64, 128, 256) and jpath in (1, 2, 3) and sp >= 1 and ms > 0
     for k in (1, 17, 300, 2999):
         act = nbody_ics.active_subset(n, k, 1540 + k)
         out = sim.force_block(torch.as_tensor(act, device=sim.device))
@@ -176,3 +176,39 @@ def test_force_full_size_sampled(precision):
     idx = torch.as_tensor(sample.astype(np.int64), device=sim.device)
     got = {k: t[..., idx] for k, t in out.items()}
     _check(got, ref, 6, precision, sample.size)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_wave_split_kernel_parity(small_case, order, precision):
+    """The wave j-split kernel (j path 3: 1, 4 or 16 rows per wave, each row's
+    j range spread over 64, 16 or 4 lanes) on small active sets, including
+    the black holes (unsoftened pair) and ragged row counts, with one split
+    and with many; errors pooled over all rows of all sets."""
+    model, eps2, n_hard, d = small_case
+    n = model.n
+    sim = _sim(model, order, precision, eps2, n_hard, d)
+    sets = [np.array([0], np.int32), np.array([1, 0], np.int32), np.array([n - 1], np.int32),
+            nbody_ics.active_subset(n, 3, 1561), nbody_ics.active_subset(n, 4, 1562),
+            nbody_ics.active_subset(n, 7, 1563), nbody_ics.active_subset(n, 16, 1564),
+            nbody_ics.active_subset(n, 17, 1565), nbody_ics.active_subset(n, 64, 1566)]
+    errs = {k: [] for k in KEYS[order] + ["pot"]}
+    for n_split in (0, 1, 7):
+        sim.set_launch(1, 64, n_split, 3)
+        for act in sets:
+            out = sim.force_block(torch.as_tensor(act, device=sim.device))
+            ref = oracle_force(order, eps2, n_hard, model.m, model.x, model.v, d[0], d[1], act=act)
+            for key in errs:
+                errs[key].append(rel_err(out[key].cpu().numpy()[..., :act.size], ref[key]))
+    for key, e in errs.items():
+        st = err_stats(np.concatenate(e))
+        say("   wave split %s p%d %-4s rms %.2e max %.2e" % (precision, order, key, st["rms"], st["max"]))
+        if precision == "fp64":
+            assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (key, st)
+        else:
+            assert st["rms"] <= LOW_TOL[key], (key, st)
+    # reruns are bitwise identical
+    act = torch.as_tensor(sets[6], device=sim.device)
+    a1 = sim.force_block(act)["acc"].cpu().numpy()
+    a2 = sim.force_block(act)["acc"].cpu().numpy()
+    np.testing.assert_array_equal(a1, a2)
