@@ -293,7 +293,7 @@ nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out);
  * device at once), items_per_wg work items aimed for per workgroup (1..16,
  * 0 = 4: each step's padded work is cut into about force_grid * items_per_wg
  * items of equal cost, at most 16384, by splitting each cluster's j-range
- * into pieces of at least 512) and i_tile active rows per work item (64 or
+ * into pieces of at least 128) and i_tile active rows per work item (64 or
  * 256, 0 = 64).  Applies to later steps and captures (a captured graph keeps
  * the shape it was captured with).  Results depend on the shape only through
  * the FP64 summation order of the split partials (and, in MIXED mode, where

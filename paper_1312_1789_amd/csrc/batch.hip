@@ -150,7 +150,7 @@ __device__ int64_t block_sum(int64_t v, int64_t *sh)
 // offset, j-splits and work items.  Items are sized by cost: the step's
 // padded work W = sum_c tiles_c * itile * N_c is cut into about k_items items
 // of W / k_items pair evaluations each (a cluster's j-range is split into s_c
-// pieces of at least 512), so no item is much longer than the average and the
+// pieces of at least 128), so no item is much longer than the average and the
 // persistent kernel ends evenly.  Items are numbered in the cluster order
 // ord[] (largest clusters first).  Bound used for the partial buffer:
 // s_c <= itile N_c k_items / W + 1, so sum_c s_c a_c <= itile k_items + n.
@@ -180,7 +180,7 @@ k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ or
         const int64_t na = pl->nact[c], nn = off[c + 1] - off[c];
         const int64_t tiles = (na + itile - 1) / itile;
         int64_t sp = (int64_t(itile) * nn + w_item - 1) / w_item;
-        const int64_t sp_max = nn / 512 > 1 ? nn / 512 : 1;
+        const int64_t sp_max = nn / kMixedChunk > 1 ? nn / kMixedChunk : 1;   // pieces of at least one FP32 chunk
         sp = sp < 1 ? 1 : (sp > sp_max ? sp_max : sp);
         int64_t jc = (nn + sp - 1) / sp;
         jc = (jc + kMixedChunk - 1) / kMixedChunk * kMixedChunk;
@@ -339,7 +339,12 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
 }
 
 // Row r of the concatenated active list: sum of its cluster's split partials
-// in split order, into outputs [3][stride] (acc, jerk, snap, crackle).
+// into outputs [3][stride] (acc, jerk, snap, crackle).  Each output value is
+// owned by a group of kRedLanes consecutive lanes: lane l adds splits l,
+// l + kRedLanes, ... in order, then the group folds its sums with a fixed
+// butterfly (the order depends only on the cluster's split count).
+constexpr int kRedLanes = 16;
+
 template <int P>
 __global__ void __launch_bounds__(256)
 k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const double *__restrict__ part,
@@ -348,10 +353,13 @@ k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const
 {
     constexpr int NV = 3 * (P / 2);
     const int64_t total = pl->aoff[nc];
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total * NV;
-         t += int64_t(gridDim.x) * blockDim.x) {
-        const int cc = int(t / total);
-        const int64_t r = t - int64_t(cc) * total;
+    const int l = int(threadIdx.x) % kRedLanes;
+    const int64_t groups = int64_t(gridDim.x) * blockDim.x / kRedLanes;
+    // the lanes of a group share g, so they run the same iterations and their
+    // exchanges (within the group) always find their partners active
+    for (int64_t g = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kRedLanes; g < total * NV; g += groups) {
+        const int cc = int(g / total);
+        const int64_t r = g - int64_t(cc) * total;
         int lo = 0, hi = nc;
         while (hi - lo > 1) {
             const int mid = (lo + hi) / 2;
@@ -360,10 +368,14 @@ k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const
         const int64_t na = pl->nact[lo], q = r - pl->aoff[lo];
         const double *src = part + pl->poff[lo];
         double s = 0.0;
-        for (int sp = 0; sp < pl->split[lo]; ++sp) s += src[(int64_t(sp) * ncomp + cc) * na + q];
-        double *outs[4] = {o0, o1, o2, o3};
-        double *o = outs[cc / 3];
-        if (o) o[(cc % 3) * stride + r] = s;
+        for (int sp = l; sp < pl->split[lo]; sp += kRedLanes) s += src[(int64_t(sp) * ncomp + cc) * na + q];
+#pragma unroll
+        for (int m = kRedLanes / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+        if (l == 0) {
+            double *outs[4] = {o0, o1, o2, o3};
+            double *o = outs[cc / 3];
+            if (o) o[(cc % 3) * stride + r] = s;
+        }
     }
 }
 
@@ -425,7 +437,7 @@ hipError_t force_prec(int precision, const BatchLaunch &L, const void *rec, hipS
 template <int P>
 hipError_t reduce_p(const BatchLaunch &L, double *o0, double *o1, double *o2, double *o3, hipStream_t s)
 {
-    const unsigned g = nblk(L.n * 3 * (P / 2), 256);
+    const unsigned g = nblk(L.n * 3 * (P / 2) * kRedLanes, 256);
     hipLaunchKernelGGL((k_b_reduce<P>), dim3(g < kStrideGrid ? g : kStrideGrid), dim3(256), 0, s, L.nc, L.n, L.plan,
                        3 * (P / 2), L.part, o0, o1, o2, o3, L.n);
     return hipGetLastError();
