@@ -279,7 +279,10 @@ k_b_predict(int64_t n, const int32_t *__restrict__ cid, const int64_t *__restric
 
 // Persistent force kernel.  Each workgroup takes items from the queue until
 // it is empty; item r (in cluster rank order) is (cluster ord[rank], i-tile,
-// j-split).  Every wave reaches the exit: the queue only grows.
+// j-split).  Every wave reaches the exit: the queue only grows.  With 64-row
+// tiles, a tile of at most 16 active rows spreads each row over several
+// lanes (the wave j-split of the single-system kernel C) instead of leaving
+// most lanes idle.
 template <class Pol, int P, int BLOCK, int TILE>
 __global__ void __launch_bounds__(BLOCK)
 k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
@@ -313,6 +316,53 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
         const int64_t j0 = base + split * jc;
         const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
         const int64_t nh = n_hard < nn ? n_hard : nn;
+        const int64_t rows = (na - tile_i * BLOCK < BLOCK) ? na - tile_i * BLOCK : BLOCK;
+        if (BLOCK == 64 && rows <= 16) {
+            // few active rows in this tile: 1, 4 or 16 rows, each spread over
+            // 64, 16 or 4 lanes that take interleaved j (the split's range),
+            // folded across those lanes with a fixed butterfly
+            const int R = rows <= 1 ? 1 : (rows <= 4 ? 4 : 16);
+            const int JS = 64 / R;
+            const int r = int(threadIdx.x) / JS, sl = int(threadIdx.x) % JS;
+            const int64_t qw = tile_i * BLOCK + r;
+            const int64_t qc = qw < na ? qw : na - 1;
+            const int64_t ia = act[pl->aoff[c] + qc];
+            const int64_t i = (ia >= base && ia < base + nn) ? ia : base;
+            const typename Pol::I ipw = Pol::load(rec[i]);
+            const bool i_hard = i - base < nh;
+            using Part = typename Pol::Part;
+            double aw[13];
+            Part pw[13];
+#pragma unroll
+            for (int cc = 0; cc < 13; ++cc) {
+                aw[cc] = 0.0;
+                zero_part(pw[cc]);
+            }
+            constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk : (1 << 30);
+            int since = 0;
+            int64_t j = j0 + sl;
+            Rec nxt = rec[j < j1 ? j : j1 - 1];
+            for (; j < j1; j += JS) {
+                const Rec rj = nxt;
+                nxt = rec[j + JS < j1 ? j + JS : j1 - 1];
+                const ET el = (i_hard && j - base < nh) ? ET(0) : e2;
+                Pol::template pair<true>(ipw, rj, el, j != i, pw);
+                if (++since == CH) {
+                    flush<Part, 1>(&pw, &aw);
+                    since = 0;
+                }
+            }
+            flush<Part, 1>(&pw, &aw);
+            for (int m = JS / 2; m > 0; m >>= 1)
+#pragma unroll
+                for (int cc = 0; cc < 13; ++cc) aw[cc] += __shfl_xor(aw[cc], m, 64);
+            if (sl == 0 && r < rows) {
+                double *dst = part + pl->poff[c] + split * ncomp * na;
+#pragma unroll
+                for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + qw] = aw[cc];
+            }
+            continue;
+        }
         // this lane's active row
         const int64_t q0 = tile_i * BLOCK + threadIdx.x;
         const int64_t q = q0 < na ? q0 : na - 1;
