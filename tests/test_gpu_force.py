@@ -178,6 +178,41 @@ def test_force_full_size_sampled(precision):
     _check(got, ref, 6, precision, sample.size)
 
 
+def test_force_max_size_sampled():
+    """The largest system the C-ABI accepts, n = 2^26 (Plummer, 4th order):
+    4096 random active rows through the tiled kernels and 7 through the wave
+    j-split kernel, in FP64 and MIXED; 128 and 7 rows checked against the
+    oracle (64-bit indexing, split-count and partial-buffer caps at full
+    size)."""
+    n = 1 << 26
+    model = nbody_ics.plummer(n, 1717)
+    d = random_derivs(n, 1718, 4)
+    sample = nbody_ics.active_subset(n, 4096, 1719)
+    check = sample[:: 32]
+    tiny = nbody_ics.active_subset(n, 7, 1720)
+    ref_big = oracle_force(4, 1e-8, 0, model.m, model.x, model.v, act=check)
+    ref_tiny = oracle_force(4, 1e-8, 0, model.m, model.x, model.v, act=tiny)
+    for precision in ("fp64", "mixed"):
+        say("max-size force %s n=%d" % (precision, n))
+        sim = _sim(model, 4, precision, 1e-8, 0, d)
+        out = sim.force_block(torch.as_tensor(sample, device=sim.device), with_pot=False)
+        idx = torch.as_tensor(np.arange(0, sample.size, 32), device=sim.device)
+        got = {k: t[..., idx] for k, t in out.items() if k != "pot"}
+        for key in ("acc", "jrk"):
+            st = err_stats(rel_err(got[key].cpu().numpy(), ref_big[key]))
+            say("   %-6s %-4s rms %.2e max %.2e" % (precision, key, st["rms"], st["max"]))
+            tol = FP64_TOL["rms"] if precision == "fp64" else LOW_TOL[key]
+            assert st["rms"] <= tol, (key, st)
+        out = sim.force_block(torch.as_tensor(tiny, device=sim.device), with_pot=False)
+        for key in ("acc", "jrk"):
+            e = rel_err(out[key].cpu().numpy(), ref_tiny[key])
+            say("   %-6s %-4s (7 rows, wave j-split) max %.2e" % (precision, key, float(e.max())))
+            assert float(e.max()) <= (FP64_TOL["max"] if precision == "fp64" else 20 * LOW_TOL[key]), key
+        sim.close()
+        del sim, out
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_wave_split_kernel_parity(small_case, order, precision):
