@@ -66,9 +66,16 @@ def log(*a):
 
 
 def source_digest() -> str:
+    """Digest of the force-kernel sources with comments and blank lines
+    removed (a comment edit does not change the profiled kernel)."""
+    import re
     h = hashlib.sha256()
     for f in FORCE_SOURCES:
-        h.update(open(f, "rb").read())
+        text = open(f).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.split("\n") if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

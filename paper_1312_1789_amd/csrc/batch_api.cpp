@@ -114,7 +114,6 @@ struct nbody_batch {
     int force_grid_req;
     hipGraph_t graph;
     hipGraphExec_t exec;
-    int last_order;   // order of the last plan (its partials and forces)
 };
 
 namespace {
@@ -201,7 +200,6 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     b->lay = lay;
     b->graph = nullptr;
     b->exec = nullptr;
-    b->last_order = cfg->order;
     // clusters by decreasing size (ties by index): the largest work items first
     b->ord.resize(size_t(n_clusters));
     std::iota(b->ord.begin(), b->ord.end(), 0);
@@ -294,7 +292,6 @@ nbody_status nbody_batch_init(nbody_batch *b, nbody_state *st)
     }
     NB_HIP(nb::launch_init_levels(c, *st, st->d[0], st->d[1], b->stream));
     NB_HIP(hipMemsetAsync(L.ctr, 0, sizeof(nb::BatchCounters), b->stream));
-    b->last_order = 8;
     return NBODY_OK;
 }
 
@@ -320,7 +317,6 @@ nbody_status nbody_batch_step(nbody_batch *b, nbody_state *st, int64_t k)
         s = enqueue_step(b, *st);
         if (s != NBODY_OK) return s;
     }
-    if (k > 0) b->last_order = b->cfg.order;
     return NBODY_OK;
 }
 
@@ -355,7 +351,6 @@ nbody_status nbody_batch_replay(nbody_batch *b, int64_t k)
     if (!b->exec) return fail(NBODY_E_STATE, "nbody_batch_replay before nbody_batch_capture");
     if (k < 0) return fail(NBODY_E_INVALID, "k must be >= 0");
     for (int64_t r = 0; r < k; ++r) NB_HIP(hipGraphLaunch(b->exec, b->stream));
-    if (k > 0) b->last_order = b->cfg.order;
     return NBODY_OK;
 }
 

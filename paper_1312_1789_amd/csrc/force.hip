@@ -9,15 +9,14 @@
 // Launch shape: grid (i-tiles, j-splits).  A lane holds NI active particles
 // in registers and the block walks its split's j range; the j records reach
 // the lanes either through wave-uniform scalar loads (kernel A) or through
-// LDS tiles (kernel B).  With one split the kernel writes the final FP64
-// sums; with several, each split writes its partial sums and a second kernel
-// adds them in split order (deterministic).
+// LDS tiles (kernel B).  For active sets smaller than a wavefront, kernel C
+// spreads each active row over several lanes instead.  With one split the
+// kernel writes the final FP64 sums; with several, each split writes its
+// partial sums and a second kernel adds them in a fixed order.
 #include "pairwise.h"
 
 namespace nb {
 namespace {
-
-
 
 // --------------------------------------------------------------------------
 // Pieces shared by both force kernels.  blockIdx.x: i-tile of blockDim.x * NI
