@@ -462,12 +462,80 @@ def run_microbench(args):
     print(json.dumps(line), flush=True)
 
 
-def integrate_run(model, label, t_end_tick, hist_pass=True, **kw):
+def _state_bytes(order):
+    """Bytes of stored state the predictor reads per particle: m, t_tick and
+    x, v, a^(0..p-3) (3 doubles each).  The separate predictor also writes a
+    record that the force kernel reads back."""
+    return 8 + 8 + 3 * 8 * order
+
+
+def run_smallstep(args):
+    """Prediction of all n particles plus the force on a small active set,
+    the work of a block step with few active particles: the predictor kernel
+    followed by the wave j-split force kernel, against the one kernel that
+    predicts the j-particles in its loads."""
+    import torch
+    import nbody_ics
+    from paper_1312_1789_amd import Simulation
+    table = []
+    sizes = [1, 2, 4, 8, 16, 32]
+    for n in [int(v) for v in args.small_n.split(",")]:
+        t0 = time.perf_counter()
+        model = nbody_ics.king(n, 7.0, 23)
+        rng = np.random.default_rng(24)
+        level = rng.integers(3, 21, n).astype(np.int32)
+        T = 3 * (1 << 17) + (1 << 15)
+        dt = 1 << (20 - level.astype(np.int64))
+        t_tick = (T // dt) * dt
+        T = int((t_tick + dt).min())
+        log("[small] King W0=7 n=%d, random block state (%.1f s to generate)" % (n, time.perf_counter() - t0))
+        for order in [int(o) for o in args.micro_orders.split(",")]:
+            d = nbody_ics.random_derivs(n, 25, order)
+            for prec in ("fp64", "mixed"):
+                sim = Simulation(model.m, model.x, model.v, order=order, precision=prec, eps2=1e-8, eta=0.1)
+                sim.load_state(model.x, model.v, d, t_tick, level)
+                rec_b = {4: 64, 6: 80, 8: 112}[order] if prec == "fp64" else {4: 64, 6: 64, 8: 80}[order]
+                for k in sizes:
+                    act = torch.as_tensor(nbody_ics.active_subset(n, k, 2400 + k), device="cuda:0")
+                    out = {}
+                    ms = {}
+                    for fuse in (False, True):
+                        sim.set_fusion(fuse)
+                        o = sim.alloc_forces(k)
+                        ms[fuse], _ = _time_launches(lambda: sim.predict_force(T, act, o, with_pot=False))
+                        out[fuse] = o
+                    same = all(torch.equal(out[False][key], out[True][key]) for key in ("acc", "jrk", "snp", "crk")[: order // 2])
+                    fused_bytes = float(n) * _state_bytes(order)
+                    plain_bytes = fused_bytes + 2.0 * n * rec_b
+                    row = {"n": n, "order": order, "precision": prec, "n_act": k, "ms_plain": ms[False],
+                           "ms_fused": ms[True], "speedup": ms[False] / ms[True], "bitwise_equal": bool(same),
+                           "fused_GBps": fused_bytes / (ms[True] * 1e-3) / 1e9,
+                           "plain_GBps": plain_bytes / (ms[False] * 1e-3) / 1e9}
+                    table.append(row)
+                    log("[small] n %8d p%d %-5s n_act %3d: predict+force %.4f ms, fused %.4f ms (%.2fx), %s; "
+                        "algorithmic HBM rate fused %.0f GB/s, plain %.0f GB/s"
+                        % (n, order, prec, k, ms[False], ms[True], ms[False] / ms[True],
+                           "bitwise equal" if same else "DIFFERENT", row["fused_GBps"], row["plain_GBps"]))
+                sim.close()
+                del sim
+                torch.cuda.empty_cache()
+    line = {"metric": "predict + force time for small active sets (fused vs separate kernels)",
+            "value": float(np.mean([r["speedup"] for r in table])), "unit": "x (mean speedup)", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "King W0=7, random block state (levels 3..20), seeded derivatives; "
+                                   "n in %s, n_act 1..32" % args.small_n},
+            "table": table}
+    print(json.dumps(line), flush=True)
+
+
+def integrate_run(model, label, t_end_tick, hist_pass=True, fuse=True, **kw):
     """Integrate a Simulation to t_end_tick with nbody_step; returns the run
-    record (steps, interactions/s, N_act histogram, energies, phase times)."""
+    record (steps, interactions/s, N_act histogram, energies, phase times).
+    fuse: predictor inside the small-block force kernel (nbody_set_fusion)."""
     import torch
     from paper_1312_1789_amd import Simulation
     sim = Simulation(model.m, model.x, model.v, **kw)
+    sim.set_fusion(fuse)
     sim.init()
     E0 = sum(sim.energy())
     sim.predict(0)
@@ -562,9 +630,10 @@ def run_c2(args):
     log("workload: Plummer n=%d, 6th order, eta 0.1, to t = %.4f" % (n, t_end / 2.0 ** 20))
     kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
     runs = {}
-    for label, prec, rule in (("mixed", "mixed", 0), ("fp64_rule_order4", "fp64", 2), ("fp64", "fp64", 0)):
-        sim, runs[label] = integrate_run(model, label, t_end, hist_pass=(label == "mixed"), precision=prec,
-                                         dt_rule=rule, **kw)
+    for label, prec, rule, fuse in (("mixed", "mixed", 0, True), ("mixed_no_fusion", "mixed", 0, False),
+                                    ("fp64_rule_order4", "fp64", 2, True), ("fp64", "fp64", 0, True)):
+        sim, runs[label] = integrate_run(model, label, t_end, hist_pass=(label == "mixed"), fuse=fuse,
+                                         precision=prec, dt_rule=rule, **kw)
         sim.close()
         del sim
     runs["mixed_one_cluster_graph"] = integrate_batched_one(model, t_end, kw)
@@ -614,13 +683,14 @@ def run_c3(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "c2", "c3"], default="king1m")
+    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "smallstep", "c2", "c3"], default="king1m")
     ap.add_argument("--c2-n", type=int, default=131072)
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
     ap.add_argument("--c3-t-end", type=float, default=1.0 / 256)
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")
+    ap.add_argument("--small-n", default="131072,1048576", help="smallstep: particle counts")
     ap.add_argument("--micro-rows", type=int, default=512, help="microbench: active rows checked against the oracle")
     ap.add_argument("--micro-tune-max", type=int, default=65536,
                     help="microbench: autotune the force launch up to this n_act first (0 = untuned defaults)")
@@ -676,6 +746,9 @@ def main():
         return
     if args.workload == "microbench":
         run_microbench(args)
+        return
+    if args.workload == "smallstep":
+        run_smallstep(args)
         return
     if args.workload == "c2":
         run_c2(args)

@@ -141,6 +141,25 @@ nbody_status nbody_predict(nbody_ctx *ctx, const nbody_state *state, int64_t t_t
 nbody_status nbody_force_block(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, double *acc,
                                double *jrk, double *snp, double *crk, double *pot);
 
+/* nbody_predict followed by nbody_force_block on act_idx, with the same
+ * arguments, outputs and results bit for bit.  When the launch shape for n_act
+ * is the wave j-split kernel (jpath 3; see nbody_set_launch) and fusion is on
+ * (nbody_set_fusion; the default), one kernel does both: each workgroup
+ * predicts the j-particles of its split as it walks them (the paper's block
+ * step predicts every particle to the block time before the force, Sec.
+ * "Codes description"), so the stored state is read once and no record is
+ * written.  The records are then stale: nbody_force_block, nbody_get_predicted
+ * and nbody_autotune need a new nbody_predict.  nbody_step and nbody_run take
+ * the same route. */
+nbody_status nbody_predict_force(nbody_ctx *ctx, const nbody_state *state, int64_t t_tick, int64_t n_act,
+                                 const int32_t *act_idx, double *acc, double *jrk, double *snp, double *crk,
+                                 double *pot);
+
+/* enable = 1 (default): nbody_predict_force, nbody_step and nbody_run fold
+ * the predictor into the wave j-split force kernel; 0: they always run the
+ * predictor kernel and then the force kernel.  Results are the same. */
+nbody_status nbody_set_fusion(nbody_ctx *ctx, int32_t enable);
+
 /* Hermite corrector, interpolated higher derivatives and new time step for
  * the active particles, whose next time must be t_tick: x, v and d[] are
  * overwritten with their values at t_tick, t_tick[i] = t_tick, level[i] the
@@ -224,7 +243,8 @@ nbody_status nbody_get_tuning(nbody_ctx *ctx, int32_t max_rows, int64_t *n_act, 
  * stream.  nbody_set_timing(ctx, 1) creates the events and starts
  * accumulating; 0 stops.  nbody_get_timers writes, in milliseconds summed over
  * the timed steps: [0] scheduler, [1] host round trip between scheduling and
- * prediction, [2] predictor, [3] force (pairwise kernel and split reduction),
+ * prediction, [2] predictor, [3] force (pairwise kernel and split reduction;
+ * with the predictor inside, see nbody_predict_force, [2] is then empty),
  * [4] corrector + time step; *steps (host) = number of timed steps. */
 nbody_status nbody_set_timing(nbody_ctx *ctx, int32_t enable);
 nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5] /* host */, int64_t *steps /* host */);

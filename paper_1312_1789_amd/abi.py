@@ -38,7 +38,7 @@ def effective_dt_rule(order: int, precision: int, dt_rule: int = 0) -> int:
 #: every symbol the header declares
 EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
-    "nbody_force_block", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
+    "nbody_force_block", "nbody_predict_force", "nbody_set_fusion", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
     "nbody_autotune", "nbody_get_tuning",
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
@@ -90,6 +90,8 @@ def lib():
             "nbody_init": [P, C.POINTER(nbody_state)],
             "nbody_predict": [P, C.POINTER(nbody_state), I64],
             "nbody_force_block": [P, I64, P, P, P, P, P, P],
+            "nbody_predict_force": [P, C.POINTER(nbody_state), I64, I64, P, P, P, P, P, P],
+            "nbody_set_fusion": [P, C.c_int32],
             "nbody_correct": [P, C.POINTER(nbody_state), I64, P, I64, P, P, P, P],
             "nbody_schedule": [P, C.POINTER(nbody_state), P, C.POINTER(I64), C.POINTER(I64)],
             "nbody_step": [P, C.POINTER(nbody_state), C.POINTER(I64), C.POINTER(I64)],
@@ -170,6 +172,17 @@ def nbody_force_block(ctx: int, n_act: int, act_idx: int, acc: int, jrk: int, sn
     P = C.c_void_p
     _check(lib().nbody_force_block(P(ctx), int(n_act), P(act_idx), P(acc), P(jrk), P(snp or None),
                                    P(crk or None), P(pot or None)), "nbody_force_block")
+
+
+def nbody_predict_force(ctx: int, st: nbody_state, t_tick: int, n_act: int, act_idx: int, acc: int, jrk: int,
+                        snp: int = 0, crk: int = 0, pot: int = 0) -> None:
+    P = C.c_void_p
+    _check(lib().nbody_predict_force(P(ctx), C.byref(st), int(t_tick), int(n_act), P(act_idx), P(acc), P(jrk),
+                                     P(snp or None), P(crk or None), P(pot or None)), "nbody_predict_force")
+
+
+def nbody_set_fusion(ctx: int, enable: int) -> None:
+    _check(lib().nbody_set_fusion(C.c_void_p(ctx), int(enable)), "nbody_set_fusion")
 
 
 def nbody_correct(ctx: int, st: nbody_state, n_act: int, act_idx: int, t_tick: int, acc: int, jrk: int,

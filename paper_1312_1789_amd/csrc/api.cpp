@@ -55,8 +55,10 @@ nb::DevScalars *scalars(nbody_ctx *ctx) { return ws_at<nb::DevScalars>(ctx, ctx-
 
 int64_t hard_count(const nbody_config &c) { return c.eps2 == 0.0 ? c.n : c.n_hard; }
 
-nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec, int64_t n_act,
-                       const int32_t *act, double *acc, double *jrk, double *snp, double *crk, double *pot)
+// Force arguments and the launch shape for n_act active particles: the shape
+// set by nbody_set_launch, else the tuned table's, else the default.
+nb::ForceArgs force_args(nbody_ctx *ctx, const void *rec, int64_t n_act, const int32_t *act, double *acc,
+                         double *jrk, double *snp, double *crk, double *pot)
 {
     nb::ForceArgs a{};
     a.rec = rec;
@@ -93,9 +95,48 @@ nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec
         a.n_split = 0;
         a.jpath = n_act <= 32 ? 3 : 0;
     }
+    return a;
+}
+
+nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec, int64_t n_act,
+                       const int32_t *act, double *acc, double *jrk, double *snp, double *crk, double *pot)
+{
+    const nb::ForceArgs a = force_args(ctx, rec, n_act, act, acc, jrk, snp, crk, pot);
     int used = 0;
     NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
     ctx->stats.interactions += double(n_act) * double(ctx->cfg.n);
+    return NBODY_OK;
+}
+
+// Prediction of every particle to t followed by the force on the active set.
+// When the launch shape is the wave j-split kernel and fusion is on, one
+// kernel does both (the records are then not written); otherwise the
+// predictor kernel writes the records and the force kernel reads them.
+// *fused (may be null) tells which.
+nbody_status run_predict_force(nbody_ctx *ctx, const nbody_state *st, int64_t t, int64_t n_act, const int32_t *act,
+                               double *acc, double *jrk, double *snp, double *crk, double *pot, bool *fused)
+{
+    const nbody_config &c = ctx->cfg;
+    const nb::ForceArgs a = force_args(ctx, ctx->ws + ctx->lay.rec, n_act, act, acc, jrk, snp, crk, pot);
+    const bool f = ctx->fuse && a.jpath == 3;
+    if (fused) *fused = f;
+    int used = 0;
+    if (f) {
+        nb::PredIn in{};
+        in.m = st->m;
+        in.x = st->x;
+        in.v = st->v;
+        for (int k = 0; k < 6; ++k) in.d[k] = k <= c.order - 3 ? st->d[k] : nullptr;
+        in.t_tick = st->t_tick;
+        in.t = t;
+        ctx->predicted = false;   // the records are stale from here on
+        NB_HIP(nb::launch_force_pred(c.order, c.precision, a, in, ctx->stream, &used));
+    } else {
+        NB_HIP(nb::launch_predict(c.order, c.precision, c.n, *st, t, ctx->ws + ctx->lay.rec, ctx->stream));
+        ctx->predicted = true;
+        NB_HIP(nb::launch_force(c.order, c.precision, a, ctx->stream, &used));
+    }
+    ctx->stats.interactions += double(n_act) * double(c.n);
     return NBODY_OK;
 }
 
@@ -183,6 +224,7 @@ nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes
     ctx->ws_bytes = bytes;
     ctx->lay = L;
     ctx->predicted = false;
+    ctx->fuse = true;
     ctx->ni = 1;
     ctx->block = 256;
     ctx->n_split = 0;
@@ -403,6 +445,34 @@ nbody_status nbody_force_block(nbody_ctx *ctx, int64_t n_act, const int32_t *act
                      crk, pot);
 }
 
+nbody_status nbody_predict_force(nbody_ctx *ctx, const nbody_state *st, int64_t t_tick, int64_t n_act,
+                                 const int32_t *act_idx, double *acc, double *jrk, double *snp, double *crk,
+                                 double *pot)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    nbody_status s = check_state(ctx, st);
+    if (s != NBODY_OK) return s;
+    if (t_tick < 0) return fail(NBODY_E_INVALID, "t_tick must be >= 0");
+    if (n_act < 0 || n_act > ctx->cfg.n) return fail(NBODY_E_INVALID, "n_act must be in [0, n]");
+    if (n_act == 0) return nbody_predict(ctx, st, t_tick);
+    if (!act_idx || (reinterpret_cast<uintptr_t>(act_idx) & 3u)) return fail(NBODY_E_INVALID, "act_idx must be non-NULL, 4-byte aligned");
+    if (!acc || !jrk || !aligned8(acc) || !aligned8(jrk)) return fail(NBODY_E_INVALID, "acc and jrk must be non-NULL, 8-byte aligned");
+    const double *opt[3] = {snp, crk, pot};
+    for (const double *p : opt)
+        if (p && !aligned8(p)) return fail(NBODY_E_INVALID, "outputs must be 8-byte aligned");
+    if (ctx->cfg.order < 6) snp = nullptr;
+    if (ctx->cfg.order < 8) crk = nullptr;
+    return run_predict_force(ctx, st, t_tick, n_act, act_idx, acc, jrk, snp, crk, pot, nullptr);
+}
+
+nbody_status nbody_set_fusion(nbody_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(NBODY_E_INVALID, "enable must be 0 or 1 (got %d)", enable);
+    ctx->fuse = enable == 1;
+    return NBODY_OK;
+}
+
 nbody_status nbody_correct(nbody_ctx *ctx, nbody_state *st, int64_t n_act, const int32_t *act_idx, int64_t t_tick,
                            const double *acc, const double *jrk, const double *snp, const double *crk)
 {
@@ -478,14 +548,23 @@ nbody_status step_impl(nbody_ctx *ctx, nbody_state *st, int64_t t_limit, bool ch
     if (n_act <= 0 || n_act > c.n) return fail(NBODY_E_STATE, "scheduler found %lld active particles", (long long)n_act);
     if (t_next > t_limit) return NBODY_OK;
     if (tm) NB_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
-    s = nbody_predict(ctx, st, t_next);
-    if (s != NBODY_OK) return s;
-    if (tm) NB_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
     double *F = ws_at<double>(ctx, ctx->lay.force);
     double *acc = F, *jrk = F + 3 * n_act, *snp = F + 6 * n_act, *crk = F + 9 * n_act;
-    s = run_force(ctx, c.order, c.precision, ctx->ws + ctx->lay.rec, n_act, act, acc, jrk,
-                  c.order >= 6 ? snp : nullptr, c.order >= 8 ? crk : nullptr, nullptr);
-    if (s != NBODY_OK) return s;
+    const nb::ForceArgs shape = force_args(ctx, nullptr, n_act, act, acc, jrk, snp, crk, nullptr);
+    if (ctx->fuse && shape.jpath == 3) {
+        // predictor inside the force kernel: the predictor phase is empty
+        if (tm) NB_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+        s = run_predict_force(ctx, st, t_next, n_act, act, acc, jrk, c.order >= 6 ? snp : nullptr,
+                              c.order >= 8 ? crk : nullptr, nullptr, nullptr);
+        if (s != NBODY_OK) return s;
+    } else {
+        s = nbody_predict(ctx, st, t_next);
+        if (s != NBODY_OK) return s;
+        if (tm) NB_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+        s = run_force(ctx, c.order, c.precision, ctx->ws + ctx->lay.rec, n_act, act, acc, jrk,
+                      c.order >= 6 ? snp : nullptr, c.order >= 8 ? crk : nullptr, nullptr);
+        if (s != NBODY_OK) return s;
+    }
     if (tm) NB_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
     const double *f[4] = {acc, jrk, snp, crk};
     NB_HIP(nb::launch_correct(c, *st, n_act, act, nullptr, t_next, f, scalars(ctx), ctx->stream));

@@ -361,16 +361,41 @@ int auto_split(int64_t n, int64_t n_act, int ni, int block)
 int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath)
 {
     if (jpath != 3) return auto_split(n, n_act, ni, block);
-    // kernel C: one wave per 1, 4 or 16 rows; splits for about 8 waves per SIMD
+    // kernel C: one 64-lane workgroup per 1, 4 or 16 rows and split.  Split
+    // counts giving about 512, 1024 and 2048 workgroups were the fastest on
+    // MI355X (n = 2^17 and 2^20, orders 6 and 8, with and without the
+    // predictor inside): shorter splits cost more in per-workgroup set-up and
+    // in the split reduction than they add in parallelism.
     const int64_t rw = n_act <= 1 ? 1 : (n_act <= 4 ? 4 : 16);
-    const int64_t waves = (n_act + rw - 1) / rw;
-    int64_t sp = (256 * 4 * 8 + waves - 1) / waves;
+    const int64_t tiles = (n_act + rw - 1) / rw;
+    const int64_t target = rw == 1 ? 512 : (rw == 4 ? 1024 : 2048);
+    int64_t sp = (target + tiles - 1) / tiles;
     const int64_t max_by_n = n / kMixedChunk > 0 ? n / kMixedChunk : 1;
     const int64_t max_by_part = kPartEntries / (n_act > 0 ? n_act : 1);
     if (sp > max_by_n) sp = max_by_n;
     if (sp > max_by_part) sp = max_by_part;
     if (sp > 65535) sp = 65535;
     return sp < 1 ? 1 : int(sp);
+}
+
+void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int *n_split,
+                 int64_t *j_chunk)
+{
+    int sp = n_split_req > 0 ? n_split_req : auto_split_path(n, n_act, ni, block, jpath);
+    if (int64_t(sp) * n_act > kPartEntries) sp = int(kPartEntries / n_act);
+    if (sp < 1) sp = 1;
+    // split length: a multiple of the MIXED chunk so chunks never straddle splits
+    int64_t jc = (n + sp - 1) / sp;
+    jc = (jc + kMixedChunk - 1) / kMixedChunk * kMixedChunk;
+    *j_chunk = jc;
+    *n_split = int((n + jc - 1) / jc);
+}
+
+hipError_t launch_split_reduce(int order, const ForceArgs &a, int n_split, hipStream_t s)
+{
+    if (order == 4) return launch_reduce<4>(a, n_split, s);
+    if (order == 6) return launch_reduce<6>(a, n_split, s);
+    return launch_reduce<8>(a, n_split, s);
 }
 
 hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split)
@@ -380,14 +405,7 @@ hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_
     sh.block = (a.block == 64 || a.block == 128) ? a.block : 256;
     // j path: FP64 reads j records from SGPRs, the FP32 modes from LDS
     sh.jpath = a.jpath >= 1 && a.jpath <= 3 ? a.jpath : (precision == NBODY_FP64 ? 1 : 2);
-    int sp = a.n_split > 0 ? a.n_split : auto_split_path(a.n, a.n_act, sh.ni, sh.block, sh.jpath);
-    if (int64_t(sp) * a.n_act > kPartEntries) sp = int(kPartEntries / a.n_act);
-    if (sp < 1) sp = 1;
-    // split length: a multiple of the MIXED chunk so chunks never straddle splits
-    int64_t j_chunk = (a.n + sp - 1) / sp;
-    j_chunk = (j_chunk + kMixedChunk - 1) / kMixedChunk * kMixedChunk;
-    sh.j_chunk = j_chunk;
-    sh.n_split = int((a.n + j_chunk - 1) / j_chunk);
+    split_shape(a.n, a.n_act, a.n_split, sh.ni, sh.block, sh.jpath, &sh.n_split, &sh.j_chunk);
     if (used_split) *used_split = sh.n_split;
     switch (order) {
     case 4: return run_prec<4>(precision, a, s, sh);

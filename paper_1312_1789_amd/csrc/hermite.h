@@ -31,33 +31,55 @@ __device__ __forceinline__ double taylor(const double *D, double dt)
     return s;
 }
 
-// Predict particle i (state arrays [3][n]) by dt and write its record.
+// The stored state of one particle that the predictor reads: mass and, per
+// component, x, v and the stored derivatives a^(0..p-3).
+template <int P> struct PState {
+    double m;
+    double D[3][P];
+};
+
+template <int P>
+__device__ __forceinline__ PState<P> load_pstate(int64_t n, int64_t i, const double *__restrict__ m,
+                                                 const double *__restrict__ x, const double *__restrict__ v,
+                                                 const double *const *ds)
+{
+    PState<P> s;
+    s.m = m[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s.D[c][0] = x[c * n + i];
+        s.D[c][1] = v[c * n + i];
+#pragma unroll
+        for (int k = 0; k < P - 2; ++k) s.D[c][k + 2] = ds[k][c * n + i];
+    }
+    return s;
+}
+
+// The j-particle record of a stored state predicted by dt: RecF64<P> (FP64)
+// or RecDS<P> (double-single position and velocity, FP32 mass, acceleration
+// and jerk) for PREC = NBODY_FP64 or otherwise.
+template <int P, int PREC> struct PredRec { using type = RecDS<P>; };
+template <int P> struct PredRec<P, NBODY_FP64> { using type = RecF64<P>; };
+
 template <int P, int PREC>
-__device__ __forceinline__ void predict_one(int64_t n, int64_t i, double dt, const double *__restrict__ m,
-                                            const double *__restrict__ x, const double *__restrict__ v,
-                                            const double *const *ds, void *__restrict__ rec_out)
+__device__ __forceinline__ typename PredRec<P, PREC>::type predict_state(const PState<P> &s, double dt)
 {
     double xp[3], vp[3], ap[3], jp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double D[P];
-        D[0] = x[c * n + i];
-        D[1] = v[c * n + i];
-#pragma unroll
-        for (int k = 0; k < P - 2; ++k) D[k + 2] = ds[k][c * n + i];
-        xp[c] = taylor<P>(D, dt);
-        vp[c] = taylor<P - 1>(D + 1, dt);
-        if constexpr (P >= 6) ap[c] = taylor<P - 2>(D + 2, dt);
-        if constexpr (P >= 8) jp[c] = taylor<P - 3>(D + 3, dt);
+        xp[c] = taylor<P>(s.D[c], dt);
+        vp[c] = taylor<P - 1>(s.D[c] + 1, dt);
+        if constexpr (P >= 6) ap[c] = taylor<P - 2>(s.D[c] + 2, dt);
+        if constexpr (P >= 8) jp[c] = taylor<P - 3>(s.D[c] + 3, dt);
     }
-    const double mi = m[i];
+    const double mi = s.m;
     if constexpr (PREC == NBODY_FP64) {
         RecF64<P> r{};
         r.x = xp[0]; r.y = xp[1]; r.z = xp[2]; r.m = mi;
         r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
         if constexpr (P >= 6) { r.ax = ap[0]; r.ay = ap[1]; r.az = ap[2]; }
         if constexpr (P >= 8) { r.jx = jp[0]; r.jy = jp[1]; r.jz = jp[2]; }
-        static_cast<RecF64<P> *>(rec_out)[i] = r;
+        return r;
     } else {
         RecDS<P> r{};
         float hx[3], lx[3], hv[3], lv[3];
@@ -74,8 +96,29 @@ __device__ __forceinline__ void predict_one(int64_t n, int64_t i, double dt, con
         r.vxl = lv[0]; r.vyl = lv[1]; r.vzl = lv[2];
         if constexpr (P >= 6) { r.ax = float(ap[0]); r.ay = float(ap[1]); r.az = float(ap[2]); }
         if constexpr (P >= 8) { r.jx = float(jp[0]); r.jy = float(jp[1]); r.jz = float(jp[2]); }
-        static_cast<RecDS<P> *>(rec_out)[i] = r;
+        return r;
     }
+}
+
+// Particle i (state arrays [3][n]) predicted by dt.
+template <int P, int PREC>
+__device__ __forceinline__ typename PredRec<P, PREC>::type predict_rec(int64_t n, int64_t i, double dt,
+                                                                      const double *__restrict__ m,
+                                                                      const double *__restrict__ x,
+                                                                      const double *__restrict__ v,
+                                                                      const double *const *ds)
+{
+    return predict_state<P, PREC>(load_pstate<P>(n, i, m, x, v, ds), dt);
+}
+
+// Predict particle i by dt and write its record.
+template <int P, int PREC>
+__device__ __forceinline__ void predict_one(int64_t n, int64_t i, double dt, const double *__restrict__ m,
+                                            const double *__restrict__ x, const double *__restrict__ v,
+                                            const double *const *ds, void *__restrict__ rec_out)
+{
+    using Rec = typename PredRec<P, PREC>::type;
+    static_cast<Rec *>(rec_out)[i] = predict_rec<P, PREC>(n, i, dt, m, x, v, ds);
 }
 
 // --------------------------------------------------------------------------

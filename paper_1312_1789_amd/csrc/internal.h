@@ -89,6 +89,29 @@ struct ForceArgs {
 
 hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split);
 
+// j-splits and split length (a multiple of the MIXED chunk) of a force launch:
+// n_split_req > 0 is taken as given (bounded by the partial-sum scratch),
+// 0 chooses from n_act and the shape.
+void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int *n_split,
+                 int64_t *j_chunk);
+
+// Fixed-order sum of n_split partial results in a.part into a.out.
+hipError_t launch_split_reduce(int order, const ForceArgs &a, int n_split, hipStream_t s);
+
+// The stored state the predictor reads, and the time it predicts to.
+struct PredIn {
+    const double *m, *x, *v;
+    const double *d[6];      // stored derivatives a^(0..p-3), [3][n] each
+    const int64_t *t_tick;
+    int64_t t;
+};
+
+// The wave j-split force (ForceArgs.jpath 3) with the predictor in its j
+// loads: a.rec is not read; the j-particles and the active i-particles are
+// predicted from `in` to in.t, exactly as the predictor kernel writes them.
+hipError_t launch_force_pred(int order, int precision, const ForceArgs &a, const PredIn &in, hipStream_t s,
+                             int *used_split);
+
 // j-splits that give about 8 waves per SIMD for n_act rows in workgroups of
 // `block` lanes with ni rows per lane (the default when n_split is 0).
 int auto_split(int64_t n, int64_t n_act, int ni, int block);
@@ -142,6 +165,7 @@ struct nbody_ctx {
     nb::Layout lay;
     int device;
     bool predicted;
+    bool fuse;                        // predictor folded into the wave j-split force (nbody_set_fusion)
     int ni, block, n_split, jpath;   // launch shape fixed by nbody_set_launch (when manual)
     bool manual;
     bool tuned;                       // tune[] filled by nbody_autotune

@@ -106,6 +106,19 @@ class Simulation:
                               out["pot"].data_ptr() if with_pot else 0)
         return out
 
+    def predict_force(self, t_tick: int, act: torch.Tensor, out: dict | None = None, with_pot: bool = True):
+        """predict(t_tick) then force_block(act), in one kernel where the launch
+        shape allows (the records are then not written)."""
+        n_act = int(act.numel())
+        out = out if out is not None else self.alloc_forces(n_act)
+        abi.nbody_predict_force(self.ctx, self.state, t_tick, n_act, act.data_ptr(), out["acc"].data_ptr(),
+                                out["jrk"].data_ptr(), out["snp"].data_ptr(), out["crk"].data_ptr(),
+                                out["pot"].data_ptr() if with_pot else 0)
+        return out
+
+    def set_fusion(self, enable: bool = True):
+        abi.nbody_set_fusion(self.ctx, 1 if enable else 0)
+
     def correct(self, act: torch.Tensor, t_tick: int, f: dict):
         abi.nbody_correct(self.ctx, self.state, int(act.numel()), act.data_ptr(), t_tick, f["acc"].data_ptr(),
                           f["jrk"].data_ptr(), f["snp"].data_ptr(), f["crk"].data_ptr())

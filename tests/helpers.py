@@ -45,6 +45,17 @@ def random_derivs(n, seed, order):
     return nbody_ics.random_derivs(n, seed, order)
 
 
+def random_block_state(n, seed, k_min=3, k_max=20):
+    """Valid block-step times: t_i a multiple of dt_i = 2^-level_i, all
+    t_i <= T and t_i + dt_i > T for T = 3 * 2^-k_min + 2^-5."""
+    rng = np.random.default_rng(seed)
+    level = rng.integers(k_min, k_max + 1, n).astype(np.int32)
+    T = 3 * (TICKS >> k_min) + (TICKS >> 5)
+    dt = (1 << (20 - level.astype(np.int64)))
+    t = (T // dt) * dt
+    return t.astype(np.int64), level
+
+
 def oracle_force(order, eps2, n_hard, m, x, v, a=None, j=None, act=None):
     return oracle.force(OracleConfig(order=order, eps2=eps2, n_hard=n_hard), m, x, v,
                         a if order >= 6 else None, j if order >= 8 else None, act=act)

@@ -13,7 +13,7 @@ import torch
 
 import nbody_ics
 import oracle
-from helpers import TICKS, compare_corrected, err_stats, oracle_correct, rel_err, say
+from helpers import TICKS, compare_corrected, err_stats, oracle_correct, random_block_state, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -37,22 +37,11 @@ def _ostate(h, order):
                         h["level"].copy())
 
 
-def _random_block_state(n, seed, k_min=3, k_max=20):
-    """Valid block-step times: t_i a multiple of dt_i, all t_i + dt_i >= T."""
-    rng = np.random.default_rng(seed)
-    level = rng.integers(k_min, k_max + 1, n).astype(np.int32)
-    T = 3 * (TICKS >> k_min) + (TICKS >> 5)
-    dt = (1 << (20 - level.astype(np.int64)))
-    # latest multiple of dt not after T, minus 0 or 1 steps is not allowed:
-    t = (T // dt) * dt
-    return t.astype(np.int64), level
-
-
 def test_schedule_exact():
     for n, seed in [(1, 1), (1000, 2), (5003, 3), (70000, 4)]:
         model = nbody_ics.plummer(max(n, 2), seed)
         sim = _sim(model, 4)
-        t, lv = _random_block_state(model.n, seed)
+        t, lv = random_block_state(model.n, seed)
         sim.load_state(model.x, model.v, [np.zeros((3, model.n))] * 2, t, lv)
         t_next, act = sim.schedule()
         nxt = t + (1 << (20 - lv.astype(np.int64)))
@@ -71,7 +60,7 @@ def test_predict_parity(order, precision):
     sim = _sim(model, order, precision)
     rng = np.random.default_rng(32)
     d = [rng.normal(size=(3, n)) * 4.0 ** k for k in range(order - 2)]
-    t, lv = _random_block_state(n, 33)
+    t, lv = random_block_state(n, 33)
     sim.load_state(model.x, model.v, d, t, lv)
     T = int((t + (1 << (20 - lv.astype(np.int64)))).min())
     sim.predict(T)
