@@ -241,8 +241,21 @@ k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__
     const int c = int(gg / n_act);
     const int64_t q = gg - int64_t(c) * n_act;
     double s = 0.0;
-    if (valid)
-        for (int sp = l; sp < n_split; sp += L) s += part[(int64_t(sp) * NC + c) * n_act + q];
+    if (valid) {
+        // the loads of eight splits are issued together (one memory round
+        // trip instead of eight); the values are still added in split order
+        const double *src = part + int64_t(c) * n_act + q;
+        const int64_t step = int64_t(NC) * n_act;
+        int sp = l;
+        for (; sp + 7 * L < n_split; sp += 8 * L) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[int64_t(sp + u * L) * step];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; sp < n_split; sp += L) s += src[int64_t(sp) * step];
+    }
 #pragma unroll
     for (int m = L / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
     if (!valid || l != 0) return;
