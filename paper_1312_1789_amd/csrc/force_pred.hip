@@ -64,6 +64,7 @@ k_force_wsp(PredIn in, int64_t n, const int32_t *__restrict__ act, int64_t n_act
         zero_part(p[c]);
     }
     constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk : (1 << 30);
+    static_assert(CH % R == 0, "chunk length a multiple of the rows per workgroup");
     int since = 0;
     __shared__ Rec tile[R > 1 ? 64 : 1];
     // stored state of this lane's first j-particle (lanes past j1 take j1 - 1,
@@ -92,17 +93,38 @@ k_force_wsp(PredIn in, int64_t n, const int32_t *__restrict__ act, int64_t n_act
         } else {
             tile[lane] = mine;
             __syncthreads();
+            // A full tile without the row's own particle and without hard
+            // pairs needs no per-pair checks; the chunk counter then moves by
+            // R at once (the chunk length is a multiple of R, and only the
+            // split's last tile can be partial, so the flushes fall on the
+            // same pairs as with per-pair counting).  Not with the potential:
+            // without the self-pair select the compiler may fuse m_j / r into
+            // the potential sum as one FMA, which rounds differently.
+            const bool plain = !Pol::kWithPot && cnt == 64 && (i < jt || i >= jt + 64) && !(i_hard && jt < n_hard);
+            if (plain) {
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int u = sl + k * JS;
-                if (u < cnt) {
-                    const int64_t j = jt + u;
-                    const Rec rj = tile[u];
-                    const ET el = (i_hard && j < n_hard) ? ET(0) : e2;
-                    Pol::template pair<true>(ip, rj, el, j != i, p);
-                    if (++since == CH) {
-                        flush<Part, 1>(&p, &acc);
-                        since = 0;
+                for (int k = 0; k < R; ++k) {
+                    const Rec rj = tile[sl + k * JS];
+                    Pol::template pair<false>(ip, rj, e2, true, p);
+                }
+                since += R;
+                if (since == CH) {
+                    flush<Part, 1>(&p, &acc);
+                    since = 0;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int u = sl + k * JS;
+                    if (u < cnt) {
+                        const int64_t j = jt + u;
+                        const Rec rj = tile[u];
+                        const ET el = (i_hard && j < n_hard) ? ET(0) : e2;
+                        Pol::template pair<true>(ip, rj, el, j != i, p);
+                        if (++since == CH) {
+                            flush<Part, 1>(&p, &acc);
+                            since = 0;
+                        }
                     }
                 }
             }

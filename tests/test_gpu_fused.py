@@ -64,22 +64,24 @@ def test_fused_equals_predict_then_force(block_case, order, precision):
     model, eps2, n_hard, d, t, lv, T = block_case
     n = model.n
     sim = _sim(block_case, order, precision)
-    keys = KEYS[order] + ["pot"]
-    for n_split in (0, 1, 7):
-        sim.set_launch(1, 64, n_split, 3)
-        for act_np in _sets(n):
-            act = torch.as_tensor(act_np, device=sim.device)
-            sim.set_fusion(True)
-            fused = {k: v.clone() for k, v in sim.predict_force(T, act).items()}
-            with pytest.raises(Exception):
-                sim.predicted()            # the fused call wrote no records
-            sim.set_fusion(False)
-            plain = sim.predict_force(T, act)
-            for k in keys:
-                g = fused[k][..., : act_np.size].cpu().numpy()
-                w = plain[k][..., : act_np.size].cpu().numpy()
-                assert np.array_equal(g, w), (n_split, act_np.size, k, float(np.max(np.abs(g - w))))
-    say("fused == predict + force: order %d %s, %d sets x 3 splits" % (order, precision, len(_sets(n))))
+    for with_pot in (True, False):          # the kernels without the potential are the ones steps use
+        keys = KEYS[order] + (["pot"] if with_pot else [])
+        for n_split in (0, 1, 7):
+            sim.set_launch(1, 64, n_split, 3)
+            for act_np in _sets(n):
+                act = torch.as_tensor(act_np, device=sim.device)
+                sim.set_fusion(True)
+                fused = {k: v.clone() for k, v in sim.predict_force(T, act, with_pot=with_pot).items()}
+                with pytest.raises(Exception):
+                    sim.predicted()            # the fused call wrote no records
+                sim.set_fusion(False)
+                plain = sim.predict_force(T, act, with_pot=with_pot)
+                for k in keys:
+                    g = fused[k][..., : act_np.size].cpu().numpy()
+                    w = plain[k][..., : act_np.size].cpu().numpy()
+                    assert np.array_equal(g, w), (with_pot, n_split, act_np.size, k, float(np.max(np.abs(g - w))))
+    say("fused == predict + force: order %d %s, %d sets x 3 splits, with and without the potential"
+        % (order, precision, len(_sets(n))))
     sim.close()
 
 
