@@ -661,8 +661,13 @@ def run_c3(args):
     log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d)"
         % (n_stars, t_end / 2.0 ** 20, k_min))
     x0 = model.x[:, :2].copy()
-    sim, rec = integrate_run(model, "c3", t_end, hist_pass=False, order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1,
-                             eta_start=0.01, k_min=k_min, k_max=20)
+    kw = dict(order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1, eta_start=0.01, k_min=k_min, k_max=20)
+    sim, plain = integrate_run(model, "c3, no fusion", t_end, hist_pass=False, fuse=False, **kw)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    sim, rec = integrate_run(model, "c3", t_end, hist_pass=False, **kw)
+    rec["without_fusion"] = {k: plain[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
     h = sim.to_numpy()
     sep0 = float(np.linalg.norm(x0[:, 0] - x0[:, 1]))
     sep1 = float(np.linalg.norm(h["x"][:, 0] - h["x"][:, 1]))

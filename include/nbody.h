@@ -112,7 +112,12 @@ nbody_status nbody_workspace_size(const nbody_config *cfg, size_t *bytes /* host
 /* Create a context.  workspace: DEVICE memory of at least
  * nbody_workspace_size() bytes, 256-byte aligned, owned by the caller and kept
  * alive until nbody_destroy.  stream: a hipStream_t (NULL = default stream).
- * *out (host) receives the context. */
+ * *out (host) receives the context.  The context allocates no device memory;
+ * it takes 64 bytes of pinned host memory (hipHostMalloc, coherent), into
+ * which the block-step scheduler writes its result so that nbody_step and
+ * nbody_run wait for it by polling (if that allocation fails they copy the
+ * result and synchronise the stream instead).  nbody_destroy synchronises
+ * the stream and frees it. */
 nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes, void *stream,
                           nbody_ctx **out);
 nbody_status nbody_destroy(nbody_ctx *ctx);

@@ -147,6 +147,33 @@ nbody_status read_scalars(nbody_ctx *ctx, nb::DevScalars *h)
     return NBODY_OK;
 }
 
+// The scheduler result with sequence number seq, read from the pinned host
+// copy as soon as the scheduler has written it (the later kernels of the
+// step may still run).  The wait polls host memory and, every few thousand
+// polls, the stream: a stream error is returned, and a stream that finished
+// without the result (which should not happen) falls back to the copy.
+nbody_status read_published(nbody_ctx *ctx, int64_t seq, nb::DevScalars *h)
+{
+    if (!ctx->pub_host) return read_scalars(ctx, h);
+    const nb::HostScalars *p = ctx->pub_host;
+    unsigned spins = 0;
+    while (__atomic_load_n(&p->seq, __ATOMIC_ACQUIRE) != seq) {
+        if ((++spins & 4095u) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&p->seq, __ATOMIC_ACQUIRE) == seq) break;
+                return read_scalars(ctx, h);
+            }
+            if (e != hipErrorNotReady) return fail(NBODY_E_HIP, "scheduler: %s", hipGetErrorString(e));
+        }
+    }
+    h->t_next = p->t_next;
+    h->n_act = p->n_act;
+    h->underflow = p->underflow;
+    h->nonfinite = p->nonfinite;
+    return NBODY_OK;
+}
+
 }  // namespace
 
 namespace nb {
@@ -235,6 +262,22 @@ nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipMemsetAsync(scalars(ctx), 0, sizeof(nb::DevScalars), ctx->stream);
+    // 64 bytes of pinned, coherent host memory for the scheduler result
+    // (without it the steps copy the result and synchronise instead)
+    if (e == hipSuccess &&
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->pub_host), sizeof(nb::HostScalars), hipHostMallocCoherent) ==
+            hipSuccess) {
+        ctx->pub_host->seq = 0;
+        if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->pub_dev), ctx->pub_host, 0) != hipSuccess) {
+            (void)hipHostFree(ctx->pub_host);
+            ctx->pub_host = nullptr;
+            ctx->pub_dev = nullptr;
+        }
+    } else {
+        ctx->pub_host = nullptr;
+        (void)hipGetLastError();
+    }
+    ctx->pub_seq = 0;
     if (e != hipSuccess) {
         delete ctx;
         return fail(NBODY_E_HIP, "nbody_create: %s", hipGetErrorString(e));
@@ -248,6 +291,10 @@ nbody_status nbody_destroy(nbody_ctx *ctx)
     if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
     if (ctx->ev_made)
         for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->pub_host) {
+        (void)hipStreamSynchronize(ctx->stream);   // no scheduler kernel may still write it
+        (void)hipHostFree(ctx->pub_host);
+    }
     delete ctx;
     return NBODY_OK;
 }
@@ -498,7 +545,7 @@ nbody_status nbody_schedule(nbody_ctx *ctx, const nbody_state *st, int32_t *act_
     if (s != NBODY_OK) return s;
     if (!act_idx_out) return fail(NBODY_E_INVALID, "act_idx_out is NULL");
     NB_HIP(nb::launch_schedule(ctx->cfg.n, st->t_tick, st->level, ctx->ws + ctx->lay.sched, act_idx_out,
-                               scalars(ctx), ctx->stream));
+                               scalars(ctx), nullptr, 0, ctx->stream));
     nb::DevScalars h;
     s = read_scalars(ctx, &h);
     if (s != NBODY_OK) return s;
@@ -536,11 +583,12 @@ nbody_status step_impl(nbody_ctx *ctx, nbody_state *st, int64_t t_limit, bool ch
     const bool tm = ctx->timing && ctx->ev_made;
     *stepped = false;
     if (tm) NB_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+    const int64_t seq = ++ctx->pub_seq;
     NB_HIP(nb::launch_schedule(c.n, st->t_tick, st->level, ctx->ws + ctx->lay.sched, act, scalars(ctx),
-                               ctx->stream));
+                               ctx->pub_dev, seq, ctx->stream));
     if (tm) NB_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
     nb::DevScalars h;
-    nbody_status s = read_scalars(ctx, &h);
+    nbody_status s = read_published(ctx, seq, &h);
     if (s != NBODY_OK) return s;
     s = take_counters(ctx, h, *t_prev);   // the previous corrector's counters
     if (s != NBODY_OK) return s;

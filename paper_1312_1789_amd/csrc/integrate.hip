@@ -187,7 +187,8 @@ k_sched_count(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__re
 }
 
 __global__ void __launch_bounds__(kSchedBlock)
-k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ boff, DevScalars *__restrict__ sc)
+k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ boff, DevScalars *__restrict__ sc,
+             HostScalars *__restrict__ pub, int64_t seq)
 {
     // one block: sequential chunks of kSchedBlock, scanned in LDS
     __shared__ int64_t s[kSchedBlock];
@@ -207,7 +208,19 @@ k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ bof
         carry += s[kSchedBlock - 1];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sc->n_act = carry;
+    if (threadIdx.x == 0) {
+        sc->n_act = carry;
+        if (pub) {
+            // the fields first, then (after a system-scope fence) the
+            // sequence number the host waits for
+            pub->t_next = sc->t_next;
+            pub->n_act = carry;
+            pub->underflow = sc->underflow;
+            pub->nonfinite = sc->nonfinite;
+            __threadfence_system();
+            __hip_atomic_store(&pub->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kSchedBlock)
@@ -364,7 +377,7 @@ hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t 
 }
 
 hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *level, void *scratch,
-                           int32_t *act_out, DevScalars *sc, hipStream_t s)
+                           int32_t *act_out, DevScalars *sc, HostScalars *pub, int64_t seq, hipStream_t s)
 {
     const int nb = int((n + kSchedChunk - 1) / kSchedChunk);
     int64_t *bmin = static_cast<int64_t *>(scratch);
@@ -372,7 +385,7 @@ hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *leve
     int32_t *bcnt = reinterpret_cast<int32_t *>(boff + nb);
     hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin);
     hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, nb, bcnt, sc);
-    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bcnt, nb, boff, sc);
+    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bcnt, nb, boff, sc, pub, seq);
     hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, boff, sc, act_out);
     return hipGetLastError();
 }

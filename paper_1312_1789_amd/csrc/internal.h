@@ -145,8 +145,22 @@ hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s);
 hipError_t launch_unpack(int order, int precision, int64_t n, const void *rec, double *xp, double *vp, double *ap,
                          double *jp, hipStream_t s);
 
+// The scheduler's result for the host: written by the scheduler into
+// pinned, coherent host memory, the sequence number last, so that the host
+// can wait for it by polling instead of a copy and a stream synchronisation.
+struct HostScalars {
+    int64_t t_next;
+    int64_t n_act;
+    unsigned long long underflow;
+    unsigned long long nonfinite;
+    int64_t seq;
+    int64_t pad[3];
+};
+
+// pub (device address of a HostScalars, may be null) receives the result
+// with sequence number seq.
 hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *level, void *sched_scratch,
-                           int32_t *act_out, DevScalars *sc, hipStream_t s);
+                           int32_t *act_out, DevScalars *sc, HostScalars *pub, int64_t seq, hipStream_t s);
 
 hipError_t launch_init_levels(const nbody_config &c, const nbody_state &st, const double *a, const double *j,
                               hipStream_t s);
@@ -164,6 +178,9 @@ struct nbody_ctx {
     size_t ws_bytes;
     nb::Layout lay;
     int device;
+    nb::HostScalars *pub_host;        // pinned host copy of the scheduler result (null: copy path)
+    nb::HostScalars *pub_dev;         // its device address
+    int64_t pub_seq;
     bool predicted;
     bool fuse;                        // predictor folded into the wave j-split force (nbody_set_fusion)
     int ni, block, n_split, jpath;   // launch shape fixed by nbody_set_launch (when manual)
