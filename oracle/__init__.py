@@ -10,6 +10,7 @@ from .oracle import (  # noqa: F401
     build,
     lib_path,
     force,
+    force_nb,
     predict,
     hermite_high,
     hermite_correct,

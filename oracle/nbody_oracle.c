@@ -20,7 +20,11 @@
  *     or of order 4 (the form that reads only a .. a^(3), for forces that
  *     carry single-precision noise);
  *   - block time steps: power-of-two steps, t_i always a multiple of dt_i,
- *     a step may double only when commensurate.
+ *     a step may double only when commensurate;
+ *   - neighbour-split force (Ahmad & Cohen 1973, the scheme of the paper's
+ *     second code): acceleration and jerk summed separately over the
+ *     particles inside a neighbour sphere and over the rest, with the
+ *     neighbour list.
  * Build: gcc -O2 -ffp-contract=off -fopenmp, so rounding follows the source.
  *
  * Layouts: every 3-vector array is component-major [3][n] (x[0..n) are the
@@ -143,6 +147,61 @@ int oracle_force(const oracle_config *c, int64_t n, const double *m, const doubl
             if (crk) crk[k * n_act + q] = sc[k];
         }
         if (pot) pot[q] = sp;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Force split by a neighbour sphere (the Ahmad & Cohen 1973 scheme, which the
+ * paper's second code, NBODY6++GPU, uses: Sec. "Results", the laohu tests).
+ * For active particle i with neighbour radius squared h2[q], particle j != i
+ * is a neighbour when its unsoftened squared distance |x_j - x_i|^2 is below
+ * h2[q].  The acceleration and jerk terms of each pair (as in oracle_force,
+ * softened by eps_ij) are summed separately over the neighbours (irregular
+ * part) and over the other particles (regular part), each in index order.
+ * nb_count[q] = number of neighbours; nb_list[q * max_nb + k] for
+ * k < min(nb_count[q], max_nb) = their indices in increasing order.
+ * Outputs [3][n_act] (acc_*, jrk_*), [n_act] (nb_count), [n_act][max_nb]. */
+int oracle_force_nb(const oracle_config *c, int64_t n, const double *m, const double *x, const double *v,
+                    int64_t n_act, const int32_t *act, const double *h2, int32_t max_nb, double *acc_irr,
+                    double *jrk_irr, double *acc_reg, double *jrk_reg, int32_t *nb_count, int32_t *nb_list)
+{
+    int64_t q;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (q = 0; q < n_act; ++q) {
+        const int64_t i = act[q];
+        double ai[3] = {0, 0, 0}, ji[3] = {0, 0, 0}, ar[3] = {0, 0, 0}, jr[3] = {0, 0, 0};
+        int32_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r[3], w[3];
+            for (int k = 0; k < 3; ++k) {
+                r[k] = x[k * n + j] - x[k * n + i];
+                w[k] = v[k * n + j] - v[k * n + i];
+            }
+            const int is_nb = dot3(r, r) < h2[q];
+            const double f = dot3(r, r) + pair_eps2(c, i, j);
+            const double rinv = 1.0 / sqrt(f);
+            const double mu = m[j] * rinv * rinv * rinv;
+            const double alpha = dot3(r, w) / f;
+            double *sa = is_nb ? ai : ar, *sj = is_nb ? ji : jr;
+            for (int k = 0; k < 3; ++k) {
+                const double A = mu * r[k];
+                sa[k] += A;
+                sj[k] += mu * w[k] - 3.0 * alpha * A;
+            }
+            if (is_nb) {
+                if (cnt < max_nb) nb_list[q * max_nb + cnt] = (int32_t)j;
+                ++cnt;
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            acc_irr[k * n_act + q] = ai[k];
+            jrk_irr[k * n_act + q] = ji[k];
+            acc_reg[k * n_act + q] = ar[k];
+            jrk_reg[k * n_act + q] = jr[k];
+        }
+        nb_count[q] = cnt;
     }
     return 0;
 }

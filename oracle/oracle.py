@@ -59,6 +59,8 @@ def _load():
         lib.oracle_force.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, P, P, C.c_int64, P,
                                      P, P, P, P, P]
         lib.oracle_predict.argtypes = [C.POINTER(_Config), C.POINTER(_State), C.c_int64, P, P, P, P]
+        lib.oracle_force_nb.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, C.c_int32,
+                                        P, P, P, P, P, P]
         lib.oracle_hermite_high.argtypes = [C.c_int, C.c_double, P, P, P]
         lib.oracle_hermite_high.restype = None
         lib.oracle_hermite_correct.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, P, P, P, P]
@@ -164,6 +166,30 @@ def force(cfg: OracleConfig, m, x, v, a=None, jk=None, act=None, with_pot=True):
     lib.oracle_force(C.byref(c), n, _p(m), _p(x), _p(v), _p(a), _p(jk), na, _p(act),
                      _p(out["acc"]), _p(out["jrk"]), _p(out["snp"]), _p(out["crk"]),
                      _p(out["pot"]) if with_pot else None)
+    return out
+
+
+def force_nb(cfg: OracleConfig, m, x, v, act, h2, max_nb: int):
+    """Acceleration and jerk on the active list split by neighbour spheres:
+    j != i is a neighbour of active row q when |x_j - x_i|^2 < h2[q].
+    Returns dict with acc_irr, jrk_irr (sums over the neighbours), acc_reg,
+    jrk_reg (over the others), each (3, n_act); nb_count (n_act,) and nb_list
+    (n_act, max_nb), the first min(count, max_nb) entries the neighbours in
+    increasing index order (-1 beyond)."""
+    lib = _load()
+    m = _f64(m)
+    n = m.shape[0]
+    x = _f64(x, (3, n))
+    v = _f64(v, (3, n))
+    act = np.ascontiguousarray(act, np.int32)
+    na = act.shape[0]
+    h2 = _f64(h2, (na,))
+    out = {k: np.zeros((3, na)) for k in ("acc_irr", "jrk_irr", "acc_reg", "jrk_reg")}
+    out["nb_count"] = np.zeros(na, np.int32)
+    out["nb_list"] = np.full((na, max(int(max_nb), 1)), -1, np.int32)
+    lib.oracle_force_nb(C.byref(cfg._c()), n, _p(m), _p(x), _p(v), na, _p(act), _p(h2), int(max_nb),
+                        _p(out["acc_irr"]), _p(out["jrk_irr"]), _p(out["acc_reg"]), _p(out["jrk_reg"]),
+                        _p(out["nb_count"]), _p(out["nb_list"]))
     return out
 
 
