@@ -528,6 +528,63 @@ def run_smallstep(args):
     print(json.dumps(line), flush=True)
 
 
+def run_neighbour(args):
+    """The force split by neighbour spheres with the neighbour lists (the
+    regular-force call of an Ahmad-Cohen scheme), next to the plain force call
+    on the same active rows: King W0=7, 4th order, each active row's radius
+    enclosing its nearest --nb-k particles."""
+    import torch
+    import nbody_ics
+    from paper_1312_1789_amd import Simulation
+    n = args.nb_n
+    model = nbody_ics.king(n, 7.0, 29)
+    x = torch.as_tensor(model.x, device="cuda:0")
+    table = []
+    for n_act in [int(v) for v in args.nb_act.split(",")]:
+        act_np = nbody_ics.active_subset(n, n_act, 2900 + n_act % 97)
+        act = torch.as_tensor(act_np, device="cuda:0")
+        # radius^2 half way between the k-th and (k+1)-th nearest squared distance
+        h2 = torch.empty(n_act, dtype=torch.float64, device="cuda:0")
+        for c0 in range(0, n_act, 256):
+            xi = x[:, act[c0:c0 + 256].long()]
+            d2 = ((x[:, None, :] - xi[:, :, None]) ** 2).sum(0)
+            d2[torch.arange(xi.shape[1]), act[c0:c0 + 256].long()] = float("inf")
+            v, _ = torch.topk(d2, args.nb_k + 1, dim=1, largest=False)
+            h2[c0:c0 + 256] = (v[:, -2] * v[:, -1]).sqrt()
+            del d2
+        for prec in ("fp64", "mixed"):
+            sim = Simulation(model.m, model.x, model.v, order=4, precision=prec, eps2=1e-8, eta=0.01)
+            sim.predict(0)
+            out_nb = sim.force_block_nb(act, h2, args.nb_max)
+            out = sim.alloc_forces(n_act)
+            ms_nb, _ = _time_launches(lambda: sim.force_block_nb(act, h2, args.nb_max, out_nb))
+            ms_f, _ = _time_launches(lambda: sim.force_block(act, out, with_pot=False))
+            cnt = out_nb["nb_count"].cpu().numpy()
+            tot = (out_nb["acc_irr"] + out_nb["acc_reg"] - out["acc"]).norm(dim=0) / out["acc"].norm(dim=0)
+            rate = float(n_act) * n / (ms_nb * 1e-3)
+            peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+            row = {"n": n, "n_act": n_act, "precision": prec, "ms_nb": ms_nb, "ms_force": ms_f,
+                   "interactions_per_s": rate, "frac_of_peak_43flops": 43 * rate / 1e12 / peak,
+                   "nb_mean": float(cnt.mean()), "nb_max": int(cnt.max()),
+                   "irr_plus_reg_vs_full_max": float(tot.max())}
+            table.append(row)
+            log("[nb] n %d n_act %6d %-5s: split force + lists %.4f ms (%.3e int/s, %.1f%% of peak at 43 flops), "
+                "plain force %.4f ms (%.2fx); neighbours mean %.1f max %d; |irr + reg - full| / |full| max %.1e"
+                % (n, n_act, prec, ms_nb, rate, 100 * row["frac_of_peak_43flops"], ms_f, ms_nb / ms_f,
+                   cnt.mean(), cnt.max(), row["irr_plus_reg_vs_full_max"]))
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+    line = {"metric": "neighbour-split force with neighbour lists (Ahmad-Cohen regular force), interactions/s",
+            "value": max(r["interactions_per_s"] for r in table if r["precision"] == "mixed"),
+            "unit": "interactions/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "King W0=7 n=%d, 4th order, radii enclosing the %d nearest particles, list cap %d"
+                                   % (n, args.nb_k, args.nb_max)},
+            "table": table}
+    print(json.dumps(line), flush=True)
+
+
 def integrate_run(model, label, t_end_tick, hist_pass=True, fuse=True, **kw):
     """Integrate a Simulation to t_end_tick with nbody_step; returns the run
     record (steps, interactions/s, N_act histogram, energies, phase times).
@@ -688,7 +745,7 @@ def run_c3(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "smallstep", "c2", "c3"], default="king1m")
+    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "smallstep", "neighbour", "c2", "c3"], default="king1m")
     ap.add_argument("--c2-n", type=int, default=131072)
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
@@ -696,6 +753,10 @@ def main():
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")
     ap.add_argument("--small-n", default="131072,1048576", help="smallstep: particle counts")
+    ap.add_argument("--nb-n", type=int, default=1 << 20, help="neighbour: particle count")
+    ap.add_argument("--nb-act", default="256,1024,4096,16384", help="neighbour: active-set sizes")
+    ap.add_argument("--nb-k", type=int, default=64, help="neighbour: particles inside each sphere")
+    ap.add_argument("--nb-max", type=int, default=256, help="neighbour: list capacity per row")
     ap.add_argument("--micro-rows", type=int, default=512, help="microbench: active rows checked against the oracle")
     ap.add_argument("--micro-tune-max", type=int, default=65536,
                     help="microbench: autotune the force launch up to this n_act first (0 = untuned defaults)")
@@ -754,6 +815,9 @@ def main():
         return
     if args.workload == "smallstep":
         run_smallstep(args)
+        return
+    if args.workload == "neighbour":
+        run_neighbour(args)
         return
     if args.workload == "c2":
         run_c2(args)

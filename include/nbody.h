@@ -165,6 +165,33 @@ nbody_status nbody_predict_force(nbody_ctx *ctx, const nbody_state *state, int64
  * predictor kernel and then the force kernel.  Results are the same. */
 nbody_status nbody_set_fusion(nbody_ctx *ctx, int32_t enable);
 
+/* Force on the active particles split by neighbour spheres, with the
+ * neighbour lists: the regular/irregular split of the Ahmad & Cohen (1973)
+ * scheme used by the paper's second code, NBODY6++GPU (Sec. "Results", the
+ * laohu tests), whose GPU part is exactly this: the force from the distant
+ * particles and the neighbour lists.  Order-4 contexts in FP64 or MIXED
+ * precision; reads the predicted records of the last nbody_predict.
+ * For active row q (particle i = act_idx[q]) with neighbour radius squared
+ * h2[q] (host-side meaning: h_i^2; NaN or <= 0 gives no neighbours), particle
+ * j != i is a neighbour when its unsoftened squared distance |x_j - x_i|^2,
+ * evaluated in the kernel's precision (FP64, or FP32 from the double-single
+ * differences in MIXED), is below h2[q].  The softened acceleration and jerk
+ * of every pair (as in nbody_force_block) are summed over the other particles
+ * into acc_reg, jrk_reg and over the neighbours into acc_irr, jrk_irr.
+ * Outputs (DEVICE): acc_*, jrk_* [3][n_act] FP64; nb_count[n_act] int32 =
+ * number of neighbours; nb_list[n_act][max_nb] int32 = the first
+ * min(nb_count[q], max_nb) neighbours in increasing index order (entries past
+ * them are not written).  The irregular part is summed over the list, so a
+ * row whose list was cut (nb_count[q] > max_nb) gets NaN in acc_irr and
+ * jrk_irr; its regular part is complete.  h2 (DEVICE) [n_act] FP64.  max_nb
+ * in [0, 4096]; nb_list may be NULL when max_nb is 0 (regular part and counts
+ * only).  Uses the context's force scratch: n_act * (13 + max_nb) must stay
+ * below 2^21 * 26 (about 5.4e7), else NBODY_E_INVALID (call in pieces).
+ * The sum orders are fixed, so reruns are bitwise identical. */
+nbody_status nbody_force_block_nb(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, const double *h2,
+                                  int32_t max_nb, double *acc_irr, double *jrk_irr, double *acc_reg,
+                                  double *jrk_reg, int32_t *nb_count, int32_t *nb_list);
+
 /* Hermite corrector, interpolated higher derivatives and new time step for
  * the active particles, whose next time must be t_tick: x, v and d[] are
  * overwritten with their values at t_tick, t_tick[i] = t_tick, level[i] the

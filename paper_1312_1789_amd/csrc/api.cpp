@@ -512,6 +512,55 @@ nbody_status nbody_predict_force(nbody_ctx *ctx, const nbody_state *st, int64_t 
     return run_predict_force(ctx, st, t_tick, n_act, act_idx, acc, jrk, snp, crk, pot, nullptr);
 }
 
+nbody_status nbody_force_block_nb(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, const double *h2,
+                                  int32_t max_nb, double *acc_irr, double *jrk_irr, double *acc_reg,
+                                  double *jrk_reg, int32_t *nb_count, int32_t *nb_list)
+{
+    if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");
+    const nbody_config &c = ctx->cfg;
+    if (c.order != 4) return fail(NBODY_E_INVALID, "neighbour forces need an order-4 context (got %d)", c.order);
+    if (c.precision != NBODY_FP64 && c.precision != NBODY_MIXED)
+        return fail(NBODY_E_INVALID, "neighbour forces support FP64 and MIXED precision");
+    if (!ctx->predicted) return fail(NBODY_E_STATE, "nbody_force_block_nb before nbody_predict");
+    if (n_act < 0 || n_act > c.n) return fail(NBODY_E_INVALID, "n_act must be in [0, n]");
+    if (max_nb < 0 || max_nb > nb::kMaxNeighbours)
+        return fail(NBODY_E_INVALID, "max_nb must be in [0, %d] (got %d)", nb::kMaxNeighbours, max_nb);
+    if (n_act == 0) return NBODY_OK;
+    if (!act_idx || (reinterpret_cast<uintptr_t>(act_idx) & 3u)) return fail(NBODY_E_INVALID, "act_idx must be non-NULL, 4-byte aligned");
+    if (!h2 || !aligned8(h2)) return fail(NBODY_E_INVALID, "h2 must be non-NULL, 8-byte aligned");
+    const double *outs[4] = {acc_irr, jrk_irr, acc_reg, jrk_reg};
+    for (const double *p : outs)
+        if (!p || !aligned8(p)) return fail(NBODY_E_INVALID, "force outputs must be non-NULL, 8-byte aligned");
+    if (!nb_count || (reinterpret_cast<uintptr_t>(nb_count) & 3u)) return fail(NBODY_E_INVALID, "nb_count must be non-NULL, 4-byte aligned");
+    if (max_nb > 0 && (!nb_list || (reinterpret_cast<uintptr_t>(nb_list) & 3u)))
+        return fail(NBODY_E_INVALID, "nb_list must be non-NULL, 4-byte aligned when max_nb > 0");
+    const int64_t scratch = int64_t(nb::kPartEntries) * nb::kMaxComp * int64_t(sizeof(double));
+    const int sp = nb::nb_split(c.n, n_act, max_nb, scratch, 0);
+    if (sp < 1)
+        return fail(NBODY_E_INVALID, "n_act * (13 + max_nb) = %lld exceeds the scratch (%lld); call with fewer rows",
+                    (long long)(n_act * (13 + int64_t(max_nb))), (long long)(scratch / 4));
+    nb::NbArgs a{};
+    a.rec = ctx->ws + ctx->lay.rec;
+    a.n = c.n;
+    a.act = act_idx;
+    a.n_act = n_act;
+    a.h2 = h2;
+    a.eps2 = c.eps2;
+    a.n_hard = hard_count(c);
+    a.max_nb = max_nb;
+    a.scratch = ws_at<double>(ctx, ctx->lay.part);
+    a.acc_irr = acc_irr;
+    a.jrk_irr = jrk_irr;
+    a.acc_reg = acc_reg;
+    a.jrk_reg = jrk_reg;
+    a.nb_count = nb_count;
+    a.nb_list = nb_list;
+    int used = 0;
+    NB_HIP(nb::launch_force_nb(c.precision, a, sp, ctx->stream, &used));
+    ctx->stats.interactions += double(n_act) * double(c.n);
+    return NBODY_OK;
+}
+
 nbody_status nbody_set_fusion(nbody_ctx *ctx, int32_t enable)
 {
     if (!ctx) return fail(NBODY_E_INVALID, "ctx is NULL");

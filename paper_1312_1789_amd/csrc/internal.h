@@ -31,6 +31,7 @@ constexpr int kSchedChunk = kSchedBlock * kSchedPerThread;
 constexpr int kMixedChunk = 128;            // FP32 partial-sum length in MIXED mode
 constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act_pad * n_split)
 constexpr int kMaxComp = 13;                // acc3 + jerk3 + snap3 + crackle3 + pot
+constexpr int kMaxNeighbours = 4096;        // neighbour-list capacity per row, at most
 
 // Time-step rule in use (orders 6, 8): 1 = generalised criterion of the
 // scheme's order, 2 = its order-4 form.  dt_rule 0 picks the order-4 form
@@ -111,6 +112,27 @@ struct PredIn {
 // predicted from `in` to in.t, exactly as the predictor kernel writes them.
 hipError_t launch_force_pred(int order, int precision, const ForceArgs &a, const PredIn &in, hipStream_t s,
                              int *used_split);
+
+// Force split by neighbour spheres (order-4 terms) with the neighbour lists.
+struct NbArgs {
+    const void *rec;        // predicted records (order 4)
+    int64_t n;
+    const int32_t *act;
+    int64_t n_act;
+    const double *h2;       // neighbour radius squared per active row
+    double eps2;
+    int64_t n_hard;         // already n when eps2 == 0
+    int max_nb;             // list capacity per row
+    double *scratch;        // partial sums and per-split lists
+    double *acc_irr, *jrk_irr, *acc_reg, *jrk_reg;   // [3][n_act]
+    int32_t *nb_count;      // [n_act]
+    int32_t *nb_list;       // [n_act][max_nb] (may be null when max_nb == 0)
+};
+// Scratch bytes per (split, row); the split count for a scratch of the given
+// size (0 when it cannot hold one split); the launch (FP64 or MIXED).
+int64_t nb_scratch_per_row(int max_nb);
+int nb_split(int64_t n, int64_t n_act, int max_nb, int64_t scratch_bytes, int n_split_req);
+hipError_t launch_force_nb(int precision, const NbArgs &a, int n_split, hipStream_t s, int *used_split);
 
 // j-splits that give about 8 waves per SIMD for n_act rows in workgroups of
 // `block` lanes with ni rows per lane (the default when n_split is 0).

@@ -116,6 +116,23 @@ class Simulation:
                                 out["pot"].data_ptr() if with_pot else 0)
         return out
 
+    def force_block_nb(self, act: torch.Tensor, h2: torch.Tensor, max_nb: int, out: dict | None = None):
+        """Forces on the active indices split by neighbour spheres (h2: FP64
+        device tensor, one radius squared per row) from the last prediction;
+        returns acc_irr, jrk_irr, acc_reg, jrk_reg (3, n_act), nb_count
+        (n_act,) and nb_list (n_act, max_nb) (int32; -1 past the written
+        entries when out is not given)."""
+        n_act = int(act.numel())
+        if out is None:
+            z = lambda: torch.empty((3, n_act), dtype=torch.float64, device=self.device)
+            out = {"acc_irr": z(), "jrk_irr": z(), "acc_reg": z(), "jrk_reg": z(),
+                   "nb_count": torch.empty(n_act, dtype=torch.int32, device=self.device),
+                   "nb_list": torch.full((n_act, max(max_nb, 1)), -1, dtype=torch.int32, device=self.device)}
+        abi.nbody_force_block_nb(self.ctx, n_act, act.data_ptr(), h2.data_ptr(), max_nb, out["acc_irr"].data_ptr(),
+                                 out["jrk_irr"].data_ptr(), out["acc_reg"].data_ptr(), out["jrk_reg"].data_ptr(),
+                                 out["nb_count"].data_ptr(), out["nb_list"].data_ptr() if max_nb > 0 else 0)
+        return out
+
     def set_fusion(self, enable: bool = True):
         abi.nbody_set_fusion(self.ctx, 1 if enable else 0)
 

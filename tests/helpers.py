@@ -56,6 +56,30 @@ def random_block_state(n, seed, k_min=3, k_max=20):
     return t.astype(np.int64), level
 
 
+def band_free_radii(x, act, seed, k_max=40, min_margin=1e-4):
+    """h^2 per active particle in a gap of its sorted squared distances: k
+    neighbours (k drawn in 0..k_max, moved up to the next gap at least
+    2 min_margin wide in relative terms), h^2 at the geometric middle of the
+    gap.  Also returns each sphere's relative distance to the nearest pair."""
+    rng = np.random.default_rng(seed)
+    h2 = np.zeros(act.size)
+    margin = np.zeros(act.size)
+    for q, i in enumerate(act):
+        d2 = np.sum((x - x[:, i:i + 1]) ** 2, axis=0)
+        d2[i] = np.inf
+        s = np.sort(d2)
+        k = int(rng.integers(0, k_max + 1))
+        while True:
+            lo = s[k - 1] if k > 0 else s[0] * 0.25
+            hi = s[k]
+            h2[q] = np.sqrt(lo * hi)
+            margin[q] = min(h2[q] / lo - 1.0, 1.0 - h2[q] / hi)
+            if margin[q] >= min_margin:
+                break
+            k += 1
+    return h2, margin
+
+
 def oracle_force(order, eps2, n_hard, m, x, v, a=None, j=None, act=None):
     return oracle.force(OracleConfig(order=order, eps2=eps2, n_hard=n_hard), m, x, v,
                         a if order >= 6 else None, j if order >= 8 else None, act=act)

@@ -74,6 +74,7 @@ def test_null_context_is_rejected():
     assert L.nbody_autotune(None, 16, 1) == abi.NBODY_E_INVALID
     assert L.nbody_get_tuning(None, 0, None, None, None, None) == abi.NBODY_E_INVALID
     assert L.nbody_set_fusion(None, 1) == abi.NBODY_E_INVALID
+    assert L.nbody_force_block_nb(None, 0, None, None, 0, None, None, None, None, None, None) == abi.NBODY_E_INVALID
     assert L.nbody_predict_force(None, None, 0, 0, None, None, None, None, None, None) == abi.NBODY_E_INVALID
 
 

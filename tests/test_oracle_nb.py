@@ -18,26 +18,8 @@ import numpy as np
 
 import nbody_ics
 import oracle
+from helpers import band_free_radii
 from oracle import OracleConfig
-
-
-def band_free_radii(x, act, seed, k_max=40):
-    """h^2 per active particle between the k-th and (k+1)-th smallest squared
-    distance (k random in 0..k_max), at the geometric middle of that gap, and
-    the gap's relative half-width (how far any pair is from the sphere)."""
-    rng = np.random.default_rng(seed)
-    h2 = np.zeros(act.size)
-    margin = np.zeros(act.size)
-    for q, i in enumerate(act):
-        d2 = np.sum((x - x[:, i:i + 1]) ** 2, axis=0)
-        d2[i] = np.inf
-        s = np.sort(d2)
-        k = int(rng.integers(0, k_max + 1))
-        lo = s[k - 1] if k > 0 else s[0] * 0.25
-        hi = s[k]
-        h2[q] = np.sqrt(lo * hi)
-        margin[q] = min(h2[q] / lo - 1.0, 1.0 - h2[q] / hi) if k > 0 else 1.0 - h2[q] / hi
-    return h2, margin
 
 
 def _case(n=400, seed=5, n_act=48):
