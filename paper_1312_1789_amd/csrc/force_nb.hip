@@ -144,20 +144,47 @@ k_nb_finish(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t 
     const int64_t q = blockIdx.x;
     const int l = int(threadIdx.x);
     if (l < 6) {
+        // the loads of eight splits in flight together, added in split order
+        const double *src = part + int64_t(l) * n_act + q;
+        const int64_t step = 6 * n_act;
         double s = 0.0;
-        for (int sp = 0; sp < n_split; ++sp) s += part[(int64_t(sp) * 6 + l) * n_act + q];
+        int sp = 0;
+        for (; sp + 8 <= n_split; sp += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[int64_t(sp + u) * step];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; sp < n_split; ++sp) s += src[int64_t(sp) * step];
         (l < 3 ? acc_reg : jrk_reg)[(l % 3) * n_act + q] = s;
     }
+    // the lists: 64 splits at a time, lane l taking split s0 + l; a prefix sum
+    // over the lanes places each split's entries after those of the splits
+    // before it, and at most max_nb entries are kept in all
     int64_t total = 0;
     int written = 0;
-    for (int sp = 0; sp < n_split; ++sp) {
-        const int c = seg_cnt[int64_t(sp) * n_act + q];
+    for (int s0 = 0; s0 < n_split; s0 += 64) {
+        const int sp = s0 + l;
+        const int c = sp < n_split ? seg_cnt[int64_t(sp) * n_act + q] : 0;
         const int stored = c < max_nb ? c : max_nb;
-        const int take = stored < max_nb - written ? stored : max_nb - written;
-        const int32_t *src = seg + (int64_t(sp) * n_act + q) * max_nb;
-        for (int k = l; k < take; k += 64) nb_list[q * max_nb + written + k] = src[k];
-        written += take;
-        total += c;
+        int incl = stored;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (l >= o) incl += t;
+        }
+        const int base = written + (incl - stored);
+        const int room = max_nb - base;
+        const int take = room <= 0 ? 0 : (stored < room ? stored : room);
+        const int32_t *src = seg + (int64_t(sp < n_split ? sp : 0) * n_act + q) * max_nb;
+        for (int k = 0; k < take; ++k) nb_list[q * max_nb + base + k] = src[k];
+        const int all = __shfl(incl, 63, 64);
+        written = written + all < max_nb ? written + all : max_nb;
+        int64_t cs = c;
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) cs += __shfl_xor(cs, m, 64);
+        total += cs;
     }
     if (l == 0) nb_count[q] = int32_t(total);
     __syncthreads();   // the row's list is complete in memory
