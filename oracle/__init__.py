@@ -11,6 +11,8 @@ from .oracle import (  # noqa: F401
     lib_path,
     force,
     force_nb,
+    pn_rel,
+    pn,
     predict,
     hermite_high,
     hermite_correct,

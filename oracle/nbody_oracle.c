@@ -24,7 +24,12 @@
  *   - neighbour-split force (Ahmad & Cohen 1973, the scheme of the paper's
  *     second code): acceleration and jerk summed separately over the
  *     particles inside a neighbour sphere and over the rest, with the
- *     neighbour list.
+ *     neighbour list;
+ *   - post-Newtonian corrections between black holes (the paper's relativistic
+ *     corrections for its black-hole binaries, Introduction): the 1PN and
+ *     2.5PN terms of the two-body relative acceleration in harmonic
+ *     coordinates (Blanchet 2014, Living Rev. Relativ. 17, 2, the A and B
+ *     coefficients), added pairwise to the hard particles.
  * Build: gcc -O2 -ffp-contract=off -fopenmp, so rounding follows the source.
  *
  * Layouts: every 3-vector array is component-major [3][n] (x[0..n) are the
@@ -51,6 +56,9 @@ typedef struct {
     int k_min, k_max; /* levels allowed: dt in [2^-k_max, 2^-k_min] */
     int dt_rule;      /* orders 6, 8: 1 = generalised criterion of the scheme's order,
                          2 = its order-4 form (reads a .. a^(3) only) */
+    double c_light;   /* speed of light in the model's units; > 0 turns the
+                         post-Newtonian terms of hard pairs on */
+    int pn_terms;     /* which: 1 = 1PN, 4 = 2.5PN (radiation reaction), 5 = both */
 } oracle_config;
 
 /* Particle state.  d[k] is the k-th derivative of the acceleration a^(k)
@@ -202,6 +210,99 @@ int oracle_force_nb(const oracle_config *c, int64_t n, const double *m, const do
             jrk_reg[k * n_act + q] = jr[k];
         }
         nb_count[q] = cnt;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Post-Newtonian terms (G = 1, speed of light c).  For a pair with total mass
+ * M, symmetric mass ratio nu = m1 m2 / M^2, relative position x = x1 - x2
+ * (r = |x|, n = x / r), relative velocity v = v1 - v2 and rdot = n.v, the
+ * relative acceleration is  -(M / r^2) [(1 + A) n + B v]  with
+ *   A_1PN   = ( -3/2 nu rdot^2 + (1 + 3 nu) v^2 - 2 (2 + nu) M / r ) / c^2
+ *   B_1PN   = ( -2 (2 - nu) rdot ) / c^2
+ *   A_2.5PN = -8/5 nu (M / r) rdot ( 17/3 M / r + 3 v^2 ) / c^5
+ *   B_2.5PN =  8/5 nu (M / r) ( 3 M / r + v^2 ) / c^5
+ * (the Newtonian part is the pair term of the direct sum).  Body 1 takes
+ * m2 / M of the correction, body 2 minus m1 / M of it.  The jerk is the time
+ * derivative of the correction along dx/dt = v, dv/dt = -M n / r^2 (the
+ * two-body Newtonian acceleration), taken with dual numbers (value,
+ * derivative), which differentiate every operation exactly. */
+typedef struct { double v, d; } dual;
+
+static dual dd(double v, double d) { dual r = {v, d}; return r; }
+static dual dadd(dual a, dual b) { return dd(a.v + b.v, a.d + b.d); }
+static dual dsub(dual a, dual b) { return dd(a.v - b.v, a.d - b.d); }
+static dual dmul(dual a, dual b) { return dd(a.v * b.v, a.d * b.v + a.v * b.d); }
+static dual dscl(double s, dual a) { return dd(s * a.v, s * a.d); }
+static dual ddiv(dual a, dual b) { return dd(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+static dual dsqrt(dual a) { const double r = sqrt(a.v); return dd(r, 0.5 * a.d / r); }
+
+void oracle_pn_rel(double M, double nu, double c, int terms, const double *x, const double *v, double *apn,
+                   double *jpn)
+{
+    const double r0 = norm3(x);
+    double an[3];
+    for (int k = 0; k < 3; ++k) an[k] = -M * x[k] / (r0 * r0 * r0);
+    dual X[3], V[3];
+    for (int k = 0; k < 3; ++k) {
+        X[k] = dd(x[k], v[k]);
+        V[k] = dd(v[k], an[k]);
+    }
+    const dual r2 = dadd(dadd(dmul(X[0], X[0]), dmul(X[1], X[1])), dmul(X[2], X[2]));
+    const dual r = dsqrt(r2);
+    dual n[3];
+    for (int k = 0; k < 3; ++k) n[k] = ddiv(X[k], r);
+    const dual rdot = dadd(dadd(dmul(n[0], V[0]), dmul(n[1], V[1])), dmul(n[2], V[2]));
+    const dual v2 = dadd(dadd(dmul(V[0], V[0]), dmul(V[1], V[1])), dmul(V[2], V[2]));
+    const dual Mr = ddiv(dd(M, 0.0), r);
+    dual A = dd(0.0, 0.0), B = dd(0.0, 0.0);
+    if (terms & 1) {
+        const double c2 = c * c;
+        dual a1 = dadd(dadd(dscl(-1.5 * nu, dmul(rdot, rdot)), dscl(1.0 + 3.0 * nu, v2)), dscl(-2.0 * (2.0 + nu), Mr));
+        A = dadd(A, dscl(1.0 / c2, a1));
+        B = dadd(B, dscl(-2.0 * (2.0 - nu) / c2, rdot));
+    }
+    if (terms & 4) {
+        const double c5 = c * c * c * c * c;
+        const dual a25 = dmul(dmul(Mr, rdot), dadd(dscl(17.0 / 3.0, Mr), dscl(3.0, v2)));
+        const dual b25 = dmul(Mr, dadd(dscl(3.0, Mr), v2));
+        A = dadd(A, dscl(-1.6 * nu / c5, a25));
+        B = dadd(B, dscl(1.6 * nu / c5, b25));
+    }
+    const dual pre = ddiv(dd(-M, 0.0), r2);
+    for (int k = 0; k < 3; ++k) {
+        const dual t = dmul(pre, dadd(dmul(A, n[k]), dmul(B, V[k])));
+        apn[k] = t.v;
+        jpn[k] = t.d;
+    }
+}
+
+/* Adds the post-Newtonian terms to acc, jrk ([3][n_act]) of the active hard
+ * particles (index below n_hard), one pair at a time with every other hard
+ * particle, from the (predicted) states x, v.  No-op unless c_light > 0. */
+int oracle_pn(const oracle_config *c, int64_t n, const double *m, const double *x, const double *v, int64_t n_act,
+              const int32_t *act, double *acc, double *jrk)
+{
+    if (!(c->c_light > 0.0) || c->pn_terms == 0) return 0;
+    const int64_t nh = c->n_hard < n ? c->n_hard : n;
+    for (int64_t q = 0; q < n_act; ++q) {
+        const int64_t i = act[q];
+        if (i >= nh) continue;
+        for (int64_t k = 0; k < nh; ++k) {
+            if (k == i) continue;
+            const double M = m[i] + m[k], nu = m[i] * m[k] / (M * M);
+            double xr[3], vr[3], ap[3], jp[3];
+            for (int l = 0; l < 3; ++l) {
+                xr[l] = x[l * n + i] - x[l * n + k];
+                vr[l] = v[l * n + i] - v[l * n + k];
+            }
+            oracle_pn_rel(M, nu, c->c_light, c->pn_terms, xr, vr, ap, jp);
+            for (int l = 0; l < 3; ++l) {
+                acc[l * n_act + q] += m[k] / M * ap[l];
+                jrk[l * n_act + q] += m[k] / M * jp[l];
+            }
+        }
     }
     return 0;
 }
@@ -378,6 +479,7 @@ int oracle_init(const oracle_config *c, oracle_state *s)
     c8.order = 8;
     oracle_force(&c8, n, s->m, s->x, s->v, zero, zero, n, all, a, j, NULL, NULL, NULL);
     oracle_force(&c8, n, s->m, s->x, s->v, a, j, n, all, a2, j2, sn, cr, NULL);
+    oracle_pn(c, n, s->m, s->x, s->v, n, all, a, j);   /* hard pairs, when switched on */
     /* pass 2 recomputes a and jerk identically (they do not depend on a, jerk);
      * the pass-1 values are the ones kept */
     memcpy(s->d[0], a, sizeof(double) * 3 * n);
@@ -440,6 +542,7 @@ int64_t oracle_block_step(const oracle_config *c, oracle_state *s, int64_t *t_ne
     double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n_act * 4);
     double *acc = F, *jrk = F + 3 * n_act, *snp = F + 6 * n_act, *crk = F + 9 * n_act;
     oracle_force(c, n, s->m, xp, vp, ap, jp, n_act, act, acc, jrk, snp, crk, NULL);
+    oracle_pn(c, n, s->m, xp, vp, n_act, act, acc, jrk);
 
     int64_t under = 0, nonfinite = 0;
     int64_t qq;

@@ -38,7 +38,8 @@ def build() -> str:
 class _Config(C.Structure):
     _fields_ = [("order", C.c_int), ("eps2", C.c_double), ("n_hard", C.c_int64),
                 ("eta", C.c_double), ("eta_start", C.c_double),
-                ("k_min", C.c_int), ("k_max", C.c_int), ("dt_rule", C.c_int)]
+                ("k_min", C.c_int), ("k_max", C.c_int), ("dt_rule", C.c_int),
+                ("c_light", C.c_double), ("pn_terms", C.c_int)]
 
 
 class _State(C.Structure):
@@ -59,6 +60,9 @@ def _load():
         lib.oracle_force.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, P, P, C.c_int64, P,
                                      P, P, P, P, P]
         lib.oracle_predict.argtypes = [C.POINTER(_Config), C.POINTER(_State), C.c_int64, P, P, P, P]
+        lib.oracle_pn_rel.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P]
+        lib.oracle_pn_rel.restype = None
+        lib.oracle_pn.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, P]
         lib.oracle_force_nb.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, C.c_int32,
                                         P, P, P, P, P, P]
         lib.oracle_hermite_high.argtypes = [C.c_int, C.c_double, P, P, P]
@@ -88,10 +92,12 @@ class OracleConfig:
     k_min: int = 3
     k_max: int = 20
     dt_rule: int = 1    # orders 6, 8: 1 = generalised criterion of the order, 2 = its order-4 form
+    c_light: float = 0.0  # > 0: post-Newtonian terms between hard particles
+    pn_terms: int = 0     # 1 = 1PN, 4 = 2.5PN, 5 = both
 
     def _c(self) -> _Config:
         return _Config(self.order, self.eps2, self.n_hard, self.eta, self.eta_start, self.k_min, self.k_max,
-                       self.dt_rule)
+                       self.dt_rule, self.c_light, self.pn_terms)
 
 
 def _p(a: np.ndarray | None):
@@ -191,6 +197,32 @@ def force_nb(cfg: OracleConfig, m, x, v, act, h2, max_nb: int):
                         _p(out["acc_irr"]), _p(out["jrk_irr"]), _p(out["acc_reg"]), _p(out["jrk_reg"]),
                         _p(out["nb_count"]), _p(out["nb_list"]))
     return out
+
+
+def pn_rel(M: float, nu: float, c: float, terms: int, x, v):
+    """Post-Newtonian part of the two-body relative acceleration (1PN: terms
+    & 1, 2.5PN: terms & 4) at relative position x and velocity v, and its time
+    derivative along the Newtonian two-body motion."""
+    lib = _load()
+    x = _f64(x, (3,))
+    v = _f64(v, (3,))
+    a = np.zeros(3)
+    j = np.zeros(3)
+    lib.oracle_pn_rel(float(M), float(nu), float(c), int(terms), _p(x), _p(v), _p(a), _p(j))
+    return a, j
+
+
+def pn(cfg: OracleConfig, m, x, v, act, acc, jrk):
+    """Adds the post-Newtonian terms of the hard pairs to acc, jrk ((3, n_act)
+    arrays, modified in place) for the active list."""
+    lib = _load()
+    m = _f64(m)
+    n = m.shape[0]
+    x = _f64(x, (3, n))
+    v = _f64(v, (3, n))
+    act = np.ascontiguousarray(act, np.int32)
+    assert acc.dtype == np.float64 and acc.flags.c_contiguous and jrk.flags.c_contiguous
+    lib.oracle_pn(C.byref(cfg._c()), n, _p(m), _p(x), _p(v), act.shape[0], _p(act), _p(acc), _p(jrk))
 
 
 def predict(cfg: OracleConfig, s: State, t_tick: int):

@@ -1,0 +1,172 @@
+"""Pins of the oracle's post-Newtonian terms between black holes (the paper's
+relativistic corrections for black-hole binaries, Introduction; 1PN and 2.5PN
+two-body terms in harmonic coordinates) against results the physics fixes:
+
+* 2.5PN, circular orbit: the instantaneous power mu v.a equals the
+  quadrupole luminosity -(32/5) nu^2 (M/r)^5 / c^5;
+* 2.5PN, eccentric orbits: the orbit averages of mu v.a and of the torque
+  mu (x cross a) over a Newtonian Kepler orbit equal Peters' (1964) energy
+  and angular-momentum loss rates with their e-dependent enhancements;
+* 1PN: the circular-orbit frequency omega^2 = (M/r^3)(1 - (3 - nu) M/(c^2 r)),
+  and the periastron advance per orbit 6 pi M / (c^2 a (1 - e^2)) from
+  Gauss' perturbation equation integrated over a Kepler orbit;
+* the jerk is the time derivative of the acceleration along the two-body
+  motion (central differences of the oracle's own acceleration);
+* pairwise use conserves momentum and leaves soft particles alone;
+* the oracle's own block-step integration of a circular binary shrinks at
+  Peters' rate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleConfig
+
+
+def kepler(a, e, M, E):
+    """Relative position and velocity on a Newtonian Kepler orbit at eccentric
+    anomalies E (orbit in the x-y plane, periastron on +x)."""
+    nmean = np.sqrt(M / a ** 3)
+    Edot = nmean / (1.0 - e * np.cos(E))
+    x = np.stack([a * (np.cos(E) - e), a * np.sqrt(1 - e * e) * np.sin(E), 0 * E])
+    v = np.stack([-a * np.sin(E) * Edot, a * np.sqrt(1 - e * e) * np.cos(E) * Edot, 0 * E])
+    return x, v
+
+
+def orbit_average(f, a, e, M, npts=4096):
+    """Time average over one orbit of f(x, v): dt = (1 - e cos E) dE / n, so
+    <f> = (1/2pi) int f (1 - e cos E) dE (trapezoid rule, periodic)."""
+    E = 2 * np.pi * np.arange(npts) / npts
+    x, v = kepler(a, e, M, E)
+    vals = np.array([f(x[:, k], v[:, k]) for k in range(npts)])
+    w = 1.0 - e * np.cos(E)
+    return np.mean(vals * w)
+
+
+@pytest.mark.parametrize("M,nu,r", [(1.0, 0.25, 1.0), (0.02, 0.2, 0.2), (3.0, 0.1, 7.0)])
+def test_circular_power_is_quadrupole_luminosity(M, nu, r):
+    c = 13.0
+    v = np.sqrt(M / r)
+    x = np.array([r, 0.0, 0.0])
+    vel = np.array([0.0, v, 0.0])
+    a, _ = oracle.pn_rel(M, nu, c, 4, x, vel)
+    mu = nu * M
+    P = mu * np.dot(vel, a)
+    want = -32.0 / 5.0 * nu ** 2 * (M / r) ** 5 / c ** 5
+    assert P == pytest.approx(want, rel=1e-13)
+
+
+@pytest.mark.parametrize("e", [0.0, 0.3, 0.7])
+def test_peters_energy_and_angular_momentum_loss(e):
+    M, nu, a, c = 1.0, 0.2, 1.0, 20.0
+    mu = nu * M
+
+    def power(x, v):
+        acc, _ = oracle.pn_rel(M, nu, c, 4, x, v)
+        return mu * np.dot(v, acc)
+
+    def torque(x, v):
+        acc, _ = oracle.pn_rel(M, nu, c, 4, x, v)
+        return mu * (x[0] * acc[1] - x[1] * acc[0])
+
+    dE = orbit_average(power, a, e, M)
+    dL = orbit_average(torque, a, e, M)
+    e2 = e * e
+    dE_want = -32.0 / 5.0 * nu ** 2 * M ** 5 / (a ** 5 * c ** 5) * (1 + 73 / 24 * e2 + 37 / 96 * e2 ** 2) / (1 - e2) ** 3.5
+    dL_want = -32.0 / 5.0 * nu ** 2 * M ** 4.5 / (a ** 3.5 * c ** 5) * (1 + 7 / 8 * e2) / (1 - e2) ** 2
+    assert dE == pytest.approx(dE_want, rel=1e-9)
+    assert dL == pytest.approx(dL_want, rel=1e-9)
+
+
+@pytest.mark.parametrize("nu", [0.25, 0.09, 0.0])
+def test_1pn_circular_frequency(nu):
+    """On a circular orbit the 1PN radial term changes the centripetal
+    balance to omega^2 r = (M/r^2)(1 + A_1PN): omega^2 = (M/r^3)(1 - (3 - nu)
+    M/(c^2 r)); the velocity term vanishes (rdot = 0)."""
+    M, r, c = 1.0, 5.0, 30.0
+    v = np.sqrt(M / r)
+    a, _ = oracle.pn_rel(M, nu, c, 1, [r, 0, 0], [0, v, 0])
+    radial = -a[0] / (M / r ** 2)           # A_1PN
+    assert radial == pytest.approx(-(3 - nu) * M / (c * c * r), rel=1e-13)
+    assert abs(a[1]) < 1e-18
+
+
+@pytest.mark.parametrize("e", [0.2, 0.6])
+def test_1pn_periastron_advance(e):
+    """Gauss' equation for the argument of periastron, planar orbit:
+    d omega/dt = sqrt(p/M)/e (-R cos f + S (1 + r/p) sin f), R and S the
+    radial and transverse components of the 1PN acceleration on the Kepler
+    orbit; its integral over one period is 6 pi M / (c^2 p)."""
+    M, nu, a, c = 1.0, 0.22, 1.0, 50.0
+    p = a * (1 - e * e)
+    T = 2 * np.pi * np.sqrt(a ** 3 / M)
+
+    def domega(x, v):
+        acc, _ = oracle.pn_rel(M, nu, c, 1, x, v)
+        r = np.linalg.norm(x)
+        nvec = x / r
+        tvec = np.array([-nvec[1], nvec[0], 0.0])          # along the motion (counter-clockwise)
+        R, S = np.dot(acc, nvec), np.dot(acc, tvec)
+        cosf, sinf = x[0] / r, x[1] / r
+        return np.sqrt(p / M) / e * (-R * cosf + S * (1 + r / p) * sinf)
+
+    dw = orbit_average(domega, a, e, M) * T
+    assert dw == pytest.approx(6 * np.pi * M / (c * c * p), rel=1e-3)   # 1PN order: O(M/(c^2 p)) corrections
+
+
+def test_jerk_is_time_derivative_along_two_body_motion():
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        M, nu, c = rng.uniform(0.5, 2.0), rng.uniform(0.05, 0.25), rng.uniform(5.0, 20.0)
+        x = rng.normal(size=3)
+        v = rng.normal(size=3) * np.sqrt(M / np.linalg.norm(x))
+        an = -M * x / np.linalg.norm(x) ** 3
+        _, j = oracle.pn_rel(M, nu, c, 5, x, v)
+        h = 1e-4
+        ap, _ = oracle.pn_rel(M, nu, c, 5, x + v * h + an * h * h / 2, v + an * h)
+        am, _ = oracle.pn_rel(M, nu, c, 5, x - v * h + an * h * h / 2, v - an * h)
+        fd = (ap - am) / (2 * h)
+        np.testing.assert_allclose(j, fd, rtol=1e-6, atol=1e-9 * np.abs(j).max())
+
+
+def test_pairwise_terms_conserve_momentum_and_skip_soft_particles():
+    rng = np.random.default_rng(32)
+    n = 5
+    m = np.array([0.3, 0.1, 1e-3, 1e-3, 1e-3])
+    x = rng.normal(size=(3, n))
+    v = rng.normal(size=(3, n))
+    act = np.arange(n, dtype=np.int32)
+    acc = np.zeros((3, n))
+    jrk = np.zeros((3, n))
+    oracle.pn(OracleConfig(order=4, n_hard=2, c_light=5.0, pn_terms=5), m, x, v, act, acc, jrk)
+    np.testing.assert_allclose(m[0] * acc[:, 0] + m[1] * acc[:, 1], 0.0, atol=1e-17)
+    np.testing.assert_allclose(m[0] * jrk[:, 0] + m[1] * jrk[:, 1], 0.0, atol=1e-17)
+    assert np.all(acc[:, 2:] == 0) and np.all(jrk[:, 2:] == 0)
+    a_rel, _ = oracle.pn_rel(m[0] + m[1], m[0] * m[1] / (m[0] + m[1]) ** 2, 5.0, 5, x[:, 0] - x[:, 1], v[:, 0] - v[:, 1])
+    np.testing.assert_allclose(acc[:, 0] - acc[:, 1], a_rel, rtol=1e-14)
+    off = np.zeros((3, n))
+    oracle.pn(OracleConfig(order=4, n_hard=2, c_light=0.0, pn_terms=5), m, x, v, act, off, off.copy())
+    assert np.all(off == 0)
+
+
+def test_oracle_integration_inspiral_at_peters_rate():
+    """The oracle's 4th-order block-step integration of a circular binary
+    with the 2.5PN terms alone: the semi-major axis from the Newtonian energy
+    shrinks at Peters' rate da/dt = -(64/5) nu M^3 / (a^3 c^5)."""
+    m = np.array([0.6, 0.4])
+    M, nu, a0, c = 1.0, 0.24, 1.0, 8.0
+    x = np.array([[0.4 * a0, -0.6 * a0], [0.0, 0.0], [0.0, 0.0]])
+    vc = np.sqrt(M / a0)
+    v = np.array([[0.0, 0.0], [0.4 * vc, -0.6 * vc], [0.0, 0.0]])
+    cfg = OracleConfig(order=4, eps2=0.0, n_hard=2, eta=0.01, eta_start=0.01, k_min=3, k_max=20,
+                       c_light=c, pn_terms=4)
+    st = oracle.State(m, x, v, 4)
+    oracle.init(cfg, st)
+    T = 16.0
+    oracle.integrate(cfg, st, int(T * (1 << 20)))
+    r = np.linalg.norm(st.x[:, 0] - st.x[:, 1])
+    w = st.v[:, 0] - st.v[:, 1]
+    a1 = -M / (2.0 * (0.5 * np.dot(w, w) - M / r))
+    rate = (a1 - a0) / T
+    want = -64.0 / 5.0 * nu * M ** 3 / (a0 ** 3 * c ** 5)
+    assert rate == pytest.approx(want, rel=0.02)
