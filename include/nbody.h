@@ -80,6 +80,19 @@ typedef struct {
                            reads derivatives interpolated with weights ~ h^-(p-1); their
                            rounding noise (FP32 force terms, or FP64 at order 8) makes dt_crit
                            collapse to 2^-k_max at short steps. */
+    double c_light;     /* speed of light in the model's units (G = 1); > 0 with pn_terms != 0
+                           adds post-Newtonian terms between the hard particles (the paper's
+                           relativistic corrections for black-hole binaries, Introduction): for
+                           every pair of particles with indices < n_hard, the 1PN and / or
+                           2.5PN two-body relative acceleration in harmonic coordinates,
+                           -(M/r^2)[A n + B v] with the A, B terms of Blanchet's review
+                           (Living Rev. Relativ. 17, 2), body 1 taking m2/M of it and body 2
+                           -m1/M, and its jerk along the two-body motion; added by nbody_init,
+                           nbody_step and nbody_run to the forces of active hard particles,
+                           from their positions and velocities predicted in FP64.  Order 4
+                           only, n_hard <= 1024 (the pairs cost n_hard^2); not in the batched
+                           form (NBODY_E_UNSUPPORTED).  0 = off. */
+    int32_t pn_terms;   /* 1 = 1PN, 4 = 2.5PN (radiation reaction), 5 = both; 0 = off */
 } nbody_config;
 
 /* Particle state, DEVICE pointers, caller-owned, 8-byte aligned.

@@ -52,7 +52,8 @@ EXPORTS = (
 class nbody_config(C.Structure):
     _fields_ = [("order", C.c_int32), ("precision", C.c_int32), ("n", C.c_int64), ("n_hard", C.c_int64),
                 ("eps2", C.c_double), ("eta", C.c_double), ("eta_start", C.c_double),
-                ("k_min", C.c_int32), ("k_max", C.c_int32), ("dt_rule", C.c_int32)]
+                ("k_min", C.c_int32), ("k_max", C.c_int32), ("dt_rule", C.c_int32),
+                ("c_light", C.c_double), ("pn_terms", C.c_int32)]
 
 
 class nbody_state(C.Structure):

@@ -75,6 +75,8 @@ nbody_status check_batch(const nbody_config *cfg, int32_t nc, const int64_t *off
                          int *nb_out)
 {
     nbody_status s = nb::check_config_checked(cfg);
+    if (s == NBODY_OK && nb::pn_on(*cfg))
+        s = fail(NBODY_E_UNSUPPORTED, "post-Newtonian terms are not available in the batched form");
     if (s != NBODY_OK) return s;
     if (nc < 1 || nc > 65535) return fail(NBODY_E_INVALID, "n_clusters must be in [1, 65535] (got %d)", nc);
     if (!off) return fail(NBODY_E_INVALID, "off is NULL");

@@ -44,6 +44,9 @@ inline int dt_rule_of(const nbody_config &c)
     return (c.precision != NBODY_FP64 || c.order == 8) ? 2 : 1;
 }
 
+// Post-Newtonian terms between hard particles switched on.
+inline bool pn_on(const nbody_config &c) { return c.c_light > 0.0 && c.pn_terms != 0 && c.n_hard >= 2; }
+
 // Components of a force result for a Hermite order: 3 per derivative + pot.
 inline int n_comp(int order) { return 3 * (order / 2) + 1; }
 
@@ -163,6 +166,13 @@ hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t 
                           DevScalars *sc, hipStream_t s);
 
 hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s);
+
+// Adds the post-Newtonian terms of the hard pairs to acc, jrk ([3][n_act])
+// for the rows of act (increasing indices; the hard particles, indices below
+// n_hard, come first) predicted to t_tick (t_tick_of null: the state as it
+// is).
+hipError_t launch_pn(const nbody_config &c, const nbody_state &st, const int64_t *t_tick_of, int64_t t_tick,
+                     const int32_t *act, int64_t n_act, double *acc, double *jrk, hipStream_t s);
 
 hipError_t launch_unpack(int order, int precision, int64_t n, const void *rec, double *xp, double *vp, double *ap,
                          double *jp, hipStream_t s);

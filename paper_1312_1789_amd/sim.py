@@ -26,7 +26,8 @@ class Simulation:
 
     def __init__(self, m, x, v, order: int = 4, precision: str | int = "fp64", eps2: float = 1e-8,
                  n_hard: int = 0, eta: float = 0.01, eta_start: float = 0.01, k_min: int = 3, k_max: int = 20,
-                 device: str = "cuda:0", stream: torch.cuda.Stream | None = None, dt_rule: int = 0):
+                 device: str = "cuda:0", stream: torch.cuda.Stream | None = None, dt_rule: int = 0,
+                 c_light: float = 0.0, pn_terms: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the N-body library runs only on the device")
         self.device = torch.device(device)
@@ -36,7 +37,7 @@ class Simulation:
         self.n = n
         self.dt_rule = abi.effective_dt_rule(self.order, prec, dt_rule)
         self.cfg = abi.nbody_config(self.order, prec, n, int(n_hard), float(eps2), float(eta), float(eta_start),
-                                    int(k_min), int(k_max), int(dt_rule))
+                                    int(k_min), int(k_max), int(dt_rule), float(c_light), int(pn_terms))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.m = _dev(m, torch.float64, self.device)
         self.x = _dev(np.asarray(x).reshape(3, n), torch.float64, self.device)

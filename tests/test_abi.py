@@ -27,10 +27,11 @@ def test_library_exports_every_declared_symbol():
 
 def _cfg(**kw):
     base = dict(order=6, precision=abi.NBODY_MIXED, n=1000, n_hard=0, eps2=1e-8, eta=0.1, eta_start=0.01,
-                k_min=3, k_max=20, dt_rule=0)
+                k_min=3, k_max=20, dt_rule=0, c_light=0.0, pn_terms=0)
     base.update(kw)
     return abi.nbody_config(base["order"], base["precision"], base["n"], base["n_hard"], base["eps2"],
-                            base["eta"], base["eta_start"], base["k_min"], base["k_max"], base["dt_rule"])
+                            base["eta"], base["eta_start"], base["k_min"], base["k_max"], base["dt_rule"],
+                            base["c_light"], base["pn_terms"])
 
 
 def test_workspace_size_scales_with_n():
@@ -43,7 +44,10 @@ def test_workspace_size_scales_with_n():
 
 @pytest.mark.parametrize("kw", [dict(order=5), dict(order=10), dict(precision=3), dict(n=1), dict(n_hard=2000),
                                 dict(eps2=-1.0), dict(eta=0.0), dict(eta_start=-1.0), dict(k_min=5, k_max=4),
-                                dict(k_max=21), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1)])
+                                dict(k_max=21), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1),
+                                dict(c_light=-1.0), dict(c_light=float("inf")), dict(pn_terms=2),
+                                dict(pn_terms=3), dict(n_hard=2, c_light=10.0, pn_terms=5),   # order 6
+                                dict(order=4, n=5000, n_hard=2000, c_light=10.0, pn_terms=1)])
 def test_config_validation(kw):
     with pytest.raises(abi.NBodyError) as e:
         abi.nbody_workspace_size(_cfg(**kw))
@@ -99,6 +103,14 @@ def test_batch_validation(off, kw):
         abi.nbody_batch_workspace_size(_cfg(**kw), off)
     assert e.value.status == abi.NBODY_E_INVALID
     assert abi.last_error()
+
+
+def test_pn_config_accepted_at_order_4_and_refused_in_batches():
+    cfg = _cfg(order=4, n_hard=2, c_light=10.0, pn_terms=5)
+    assert abi.nbody_workspace_size(cfg) > 0
+    with pytest.raises(abi.NBodyError) as e:
+        abi.nbody_batch_workspace_size(_cfg(order=4, n_hard=2, c_light=10.0, pn_terms=4), [0, 500, 1000])
+    assert e.value.status == abi.NBODY_E_UNSUPPORTED
 
 
 def test_batch_too_uneven_is_unsupported():
