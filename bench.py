@@ -585,6 +585,72 @@ def run_neighbour(args):
     print(json.dumps(line), flush=True)
 
 
+def run_pn(args):
+    """Block steps of a cluster with a black-hole binary with and without the
+    post-Newtonian terms of the binary (4th order, MIXED): whole-step rate,
+    the binary's semi-major axis, and the cost of the terms; then a two-body
+    inspiral against Peters' rate."""
+    import torch
+    import nbody_ics
+    from paper_1312_1789_amd import Simulation
+    n_stars = args.pn_stars
+    model = nbody_ics.with_bh_binary(nbody_ics.king(n_stars, 7.0, 31), 0.01, 0.2)
+    t_end = int(args.pn_t_end * 2 ** 20)
+
+    def binary_a(h):
+        M = h["m"][0] + h["m"][1]
+        r = np.linalg.norm(h["x"][:, 0] - h["x"][:, 1])
+        w = h["v"][:, 0] - h["v"][:, 1]
+        return -M / (2.0 * (0.5 * np.dot(w, w) - M / r))
+
+    runs = {}
+    for label, c, terms in (("newtonian", 0.0, 0), ("pn_1_2.5", args.pn_c, 5)):
+        sim = Simulation(model.m, model.x, model.v, order=4, precision="mixed", eps2=1e-8, n_hard=2, eta=0.01,
+                         eta_start=0.01, c_light=c, pn_terms=terms)
+        sim.init()
+        a0 = binary_a(sim.to_numpy())
+        sim.predict(0)
+        sim.autotune(min(65536, model.n), 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, _ = sim.run(t_end)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = sim.stats()
+        a1 = binary_a(sim.to_numpy())
+        runs[label] = {"steps": steps, "wall_s": wall, "interactions_per_s": st.interactions / wall,
+                       "ms_per_step": wall / max(steps, 1) * 1e3, "binary_a": [a0, a1]}
+        log("[pn] %-9s %d steps to t = %.5f in %.2f s (%.3f ms/step, %.3e int/s); binary a %.6f -> %.6f"
+            % (label, steps, t_end / 2.0 ** 20, wall, runs[label]["ms_per_step"], runs[label]["interactions_per_s"],
+               a0, a1))
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    # two bodies with the 2.5PN terms alone: Peters' rate
+    m = np.array([0.6, 0.4])
+    x = np.array([[0.4, -0.6], [0.0, 0.0], [0.0, 0.0]])
+    v = np.array([[0.0, 0.0], [0.4, -0.6], [0.0, 0.0]])
+    sim = Simulation(m, x, v, order=4, precision="fp64", eps2=0.0, n_hard=2, eta=0.01, eta_start=0.01,
+                     c_light=8.0, pn_terms=4)
+    sim.init()
+    T = 16.0
+    sim.integrate(int(T * 2 ** 20))
+    h = sim.to_numpy()
+    rate = (binary_a(h) - 1.0) / T
+    peters = -64.0 / 5.0 * 0.24 / 8.0 ** 5
+    log("[pn] two-body inspiral (c = 8, 2.5PN): da/dt %.5e, Peters %.5e (ratio %.4f)" % (rate, peters, rate / peters))
+    sim.close()
+    line = {"metric": "whole-step interactions/s with post-Newtonian black-hole terms (4th order, MIXED)",
+            "value": runs["pn_1_2.5"]["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "King W0=7 %d stars + BH binary (0.01 + 0.01 at separation 0.2), c = %g, "
+                                   "t = 0 -> %.5f" % (n_stars, args.pn_c, t_end / 2.0 ** 20)},
+            "runs": runs, "pn_over_newtonian_time_per_step":
+                runs["pn_1_2.5"]["ms_per_step"] / runs["newtonian"]["ms_per_step"],
+            "two_body_inspiral": {"da_dt": rate, "peters": peters}}
+    print(json.dumps(line), flush=True)
+
+
 def integrate_run(model, label, t_end_tick, hist_pass=True, fuse=True, **kw):
     """Integrate a Simulation to t_end_tick with nbody_step; returns the run
     record (steps, interactions/s, N_act histogram, energies, phase times).
@@ -745,7 +811,7 @@ def run_c3(args):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "smallstep", "neighbour", "c2", "c3"], default="king1m")
+    ap.add_argument("--workload", choices=["king1m", "batched", "microbench", "smallstep", "neighbour", "pn", "c2", "c3"], default="king1m")
     ap.add_argument("--c2-n", type=int, default=131072)
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
@@ -757,6 +823,9 @@ def main():
     ap.add_argument("--nb-act", default="256,1024,4096,16384", help="neighbour: active-set sizes")
     ap.add_argument("--nb-k", type=int, default=64, help="neighbour: particles inside each sphere")
     ap.add_argument("--nb-max", type=int, default=256, help="neighbour: list capacity per row")
+    ap.add_argument("--pn-stars", type=int, default=1 << 18, help="pn: cluster stars")
+    ap.add_argument("--pn-c", type=float, default=1.0, help="pn: speed of light in model units")
+    ap.add_argument("--pn-t-end", type=float, default=1.0 / 64, help="pn: end time")
     ap.add_argument("--micro-rows", type=int, default=512, help="microbench: active rows checked against the oracle")
     ap.add_argument("--micro-tune-max", type=int, default=65536,
                     help="microbench: autotune the force launch up to this n_act first (0 = untuned defaults)")
@@ -818,6 +887,9 @@ def main():
         return
     if args.workload == "neighbour":
         run_neighbour(args)
+        return
+    if args.workload == "pn":
+        run_pn(args)
         return
     if args.workload == "c2":
         run_c2(args)
