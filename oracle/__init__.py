@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     force,
     force_nb,
     pn_rel,
+    pn_rel_derivs,
     pn,
     predict,
     hermite_high,

@@ -224,84 +224,146 @@ int oracle_force_nb(const oracle_config *c, int64_t n, const double *m, const do
  *   A_2.5PN = -8/5 nu (M / r) rdot ( 17/3 M / r + 3 v^2 ) / c^5
  *   B_2.5PN =  8/5 nu (M / r) ( 3 M / r + v^2 ) / c^5
  * (the Newtonian part is the pair term of the direct sum).  Body 1 takes
- * m2 / M of the correction, body 2 minus m1 / M of it.  The jerk is the time
- * derivative of the correction along dx/dt = v, dv/dt = -M n / r^2 (the
- * two-body Newtonian acceleration), taken with dual numbers (value,
- * derivative), which differentiate every operation exactly. */
-typedef struct { double v, d; } dual;
+ * m2 / M of the correction, body 2 minus m1 / M of it.  Its time derivatives
+ * (jerk, snap, crackle) are taken along the pair's Newtonian two-body motion:
+ * every quantity is carried as a truncated Taylor series in t of degree 3
+ * (coefficients f_k = f^(k)(0) / k!), the trajectory's series coming from
+ * the two-body equation x'' = -M x / |x|^3 itself, coefficient by coefficient. */
+#define TS_N 4
+typedef struct { double c[TS_N]; } tser;
 
-static dual dd(double v, double d) { dual r = {v, d}; return r; }
-static dual dadd(dual a, dual b) { return dd(a.v + b.v, a.d + b.d); }
-static dual dsub(dual a, dual b) { return dd(a.v - b.v, a.d - b.d); }
-static dual dmul(dual a, dual b) { return dd(a.v * b.v, a.d * b.v + a.v * b.d); }
-static dual dscl(double s, dual a) { return dd(s * a.v, s * a.d); }
-static dual ddiv(dual a, dual b) { return dd(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
-static dual dsqrt(dual a) { const double r = sqrt(a.v); return dd(r, 0.5 * a.d / r); }
+static tser ts_const(double v) { tser r = {{v, 0.0, 0.0, 0.0}}; return r; }
+static tser ts_add(tser a, tser b) { for (int k = 0; k < TS_N; ++k) a.c[k] += b.c[k]; return a; }
+static tser ts_scl(double s, tser a) { for (int k = 0; k < TS_N; ++k) a.c[k] *= s; return a; }
+static tser ts_mul(tser a, tser b)
+{
+    tser r;
+    for (int k = 0; k < TS_N; ++k) {
+        double t = 0.0;
+        for (int i = 0; i <= k; ++i) t += a.c[i] * b.c[k - i];
+        r.c[k] = t;
+    }
+    return r;
+}
+static tser ts_div(tser a, tser b)
+{
+    tser r;
+    for (int k = 0; k < TS_N; ++k) {
+        double t = a.c[k];
+        for (int i = 1; i <= k; ++i) t -= b.c[i] * r.c[k - i];
+        r.c[k] = t / b.c[0];
+    }
+    return r;
+}
+static tser ts_sqrt(tser a)
+{
+    tser r;
+    r.c[0] = sqrt(a.c[0]);
+    for (int k = 1; k < TS_N; ++k) {
+        double t = a.c[k];
+        for (int i = 1; i < k; ++i) t -= r.c[i] * r.c[k - i];
+        r.c[k] = t / (2.0 * r.c[0]);
+    }
+    return r;
+}
+static tser ts_dot(const tser *a, const tser *b)
+{
+    return ts_add(ts_add(ts_mul(a[0], b[0]), ts_mul(a[1], b[1])), ts_mul(a[2], b[2]));
+}
+
+/* Derivatives 0..3 of the post-Newtonian part of the relative acceleration
+ * along the two-body motion from (x, v): out[k][0..2] = d^k a_PN / dt^k. */
+void oracle_pn_rel_derivs(double M, double nu, double c, int terms, const double *x, const double *v,
+                          double out[4][3])
+{
+    /* trajectory: x(t) series to degree 4 (x4 kept apart), v(t) = x'(t) */
+    tser X[3];
+    double x4[3] = {0.0, 0.0, 0.0};
+    for (int l = 0; l < 3; ++l) {
+        X[l] = ts_const(x[l]);
+        X[l].c[1] = v[l];
+    }
+    for (int k = 0; k <= 2; ++k) {   /* the acceleration's coefficient k fixes x's coefficient k + 2 */
+        const tser r2 = ts_dot(X, X);
+        const tser r3 = ts_mul(r2, ts_sqrt(r2));
+        for (int l = 0; l < 3; ++l) {
+            const tser acc = ts_div(ts_scl(-M, X[l]), r3);
+            const double xk = acc.c[k] / ((k + 1.0) * (k + 2.0));
+            if (k + 2 < TS_N) X[l].c[k + 2] = xk;
+            else x4[l] = xk;
+        }
+    }
+    tser V[3];
+    for (int l = 0; l < 3; ++l) {
+        for (int k = 0; k < TS_N - 1; ++k) V[l].c[k] = (k + 1.0) * X[l].c[k + 1];
+        V[l].c[TS_N - 1] = TS_N * x4[l];
+    }
+    const tser r2 = ts_dot(X, X);
+    const tser r = ts_sqrt(r2);
+    tser n[3];
+    for (int l = 0; l < 3; ++l) n[l] = ts_div(X[l], r);
+    const tser rdot = ts_dot(n, V);
+    const tser v2 = ts_dot(V, V);
+    const tser Mr = ts_div(ts_const(M), r);
+    tser A = ts_const(0.0), B = ts_const(0.0);
+    if (terms & 1) {
+        const double c2 = c * c;
+        const tser a1 = ts_add(ts_add(ts_scl(-1.5 * nu, ts_mul(rdot, rdot)), ts_scl(1.0 + 3.0 * nu, v2)),
+                               ts_scl(-2.0 * (2.0 + nu), Mr));
+        A = ts_add(A, ts_scl(1.0 / c2, a1));
+        B = ts_add(B, ts_scl(-2.0 * (2.0 - nu) / c2, rdot));
+    }
+    if (terms & 4) {
+        const double c5 = c * c * c * c * c;
+        const tser a25 = ts_mul(ts_mul(Mr, rdot), ts_add(ts_scl(17.0 / 3.0, Mr), ts_scl(3.0, v2)));
+        const tser b25 = ts_mul(Mr, ts_add(ts_scl(3.0, Mr), v2));
+        A = ts_add(A, ts_scl(-1.6 * nu / c5, a25));
+        B = ts_add(B, ts_scl(1.6 * nu / c5, b25));
+    }
+    const tser pre = ts_div(ts_const(-M), r2);
+    const double fact[4] = {1.0, 1.0, 2.0, 6.0};
+    for (int l = 0; l < 3; ++l) {
+        const tser t = ts_mul(pre, ts_add(ts_mul(A, n[l]), ts_mul(B, V[l])));
+        for (int k = 0; k < TS_N; ++k) out[k][l] = fact[k] * t.c[k];
+    }
+}
 
 void oracle_pn_rel(double M, double nu, double c, int terms, const double *x, const double *v, double *apn,
                    double *jpn)
 {
-    const double r0 = norm3(x);
-    double an[3];
-    for (int k = 0; k < 3; ++k) an[k] = -M * x[k] / (r0 * r0 * r0);
-    dual X[3], V[3];
-    for (int k = 0; k < 3; ++k) {
-        X[k] = dd(x[k], v[k]);
-        V[k] = dd(v[k], an[k]);
-    }
-    const dual r2 = dadd(dadd(dmul(X[0], X[0]), dmul(X[1], X[1])), dmul(X[2], X[2]));
-    const dual r = dsqrt(r2);
-    dual n[3];
-    for (int k = 0; k < 3; ++k) n[k] = ddiv(X[k], r);
-    const dual rdot = dadd(dadd(dmul(n[0], V[0]), dmul(n[1], V[1])), dmul(n[2], V[2]));
-    const dual v2 = dadd(dadd(dmul(V[0], V[0]), dmul(V[1], V[1])), dmul(V[2], V[2]));
-    const dual Mr = ddiv(dd(M, 0.0), r);
-    dual A = dd(0.0, 0.0), B = dd(0.0, 0.0);
-    if (terms & 1) {
-        const double c2 = c * c;
-        dual a1 = dadd(dadd(dscl(-1.5 * nu, dmul(rdot, rdot)), dscl(1.0 + 3.0 * nu, v2)), dscl(-2.0 * (2.0 + nu), Mr));
-        A = dadd(A, dscl(1.0 / c2, a1));
-        B = dadd(B, dscl(-2.0 * (2.0 - nu) / c2, rdot));
-    }
-    if (terms & 4) {
-        const double c5 = c * c * c * c * c;
-        const dual a25 = dmul(dmul(Mr, rdot), dadd(dscl(17.0 / 3.0, Mr), dscl(3.0, v2)));
-        const dual b25 = dmul(Mr, dadd(dscl(3.0, Mr), v2));
-        A = dadd(A, dscl(-1.6 * nu / c5, a25));
-        B = dadd(B, dscl(1.6 * nu / c5, b25));
-    }
-    const dual pre = ddiv(dd(-M, 0.0), r2);
-    for (int k = 0; k < 3; ++k) {
-        const dual t = dmul(pre, dadd(dmul(A, n[k]), dmul(B, V[k])));
-        apn[k] = t.v;
-        jpn[k] = t.d;
+    double out[4][3];
+    oracle_pn_rel_derivs(M, nu, c, terms, x, v, out);
+    for (int l = 0; l < 3; ++l) {
+        apn[l] = out[0][l];
+        jpn[l] = out[1][l];
     }
 }
 
-/* Adds the post-Newtonian terms to acc, jrk ([3][n_act]) of the active hard
- * particles (index below n_hard), one pair at a time with every other hard
- * particle, from the (predicted) states x, v.  No-op unless c_light > 0. */
+/* Adds the post-Newtonian terms to acc, jrk (and snp, crk when not NULL)
+ * ([3][n_act]) of the active hard particles (index below n_hard), one pair at
+ * a time with every other hard particle, from the (predicted) states x, v.
+ * No-op unless c_light > 0. */
 int oracle_pn(const oracle_config *c, int64_t n, const double *m, const double *x, const double *v, int64_t n_act,
-              const int32_t *act, double *acc, double *jrk)
+              const int32_t *act, double *acc, double *jrk, double *snp, double *crk)
 {
     if (!(c->c_light > 0.0) || c->pn_terms == 0) return 0;
     const int64_t nh = c->n_hard < n ? c->n_hard : n;
+    double *outs[4] = {acc, jrk, snp, crk};
     for (int64_t q = 0; q < n_act; ++q) {
         const int64_t i = act[q];
         if (i >= nh) continue;
         for (int64_t k = 0; k < nh; ++k) {
             if (k == i) continue;
             const double M = m[i] + m[k], nu = m[i] * m[k] / (M * M);
-            double xr[3], vr[3], ap[3], jp[3];
+            double xr[3], vr[3], d[4][3];
             for (int l = 0; l < 3; ++l) {
                 xr[l] = x[l * n + i] - x[l * n + k];
                 vr[l] = v[l * n + i] - v[l * n + k];
             }
-            oracle_pn_rel(M, nu, c->c_light, c->pn_terms, xr, vr, ap, jp);
-            for (int l = 0; l < 3; ++l) {
-                acc[l * n_act + q] += m[k] / M * ap[l];
-                jrk[l * n_act + q] += m[k] / M * jp[l];
-            }
+            oracle_pn_rel_derivs(M, nu, c->c_light, c->pn_terms, xr, vr, d);
+            for (int o = 0; o < 4; ++o)
+                if (outs[o])
+                    for (int l = 0; l < 3; ++l) outs[o][l * n_act + q] += m[k] / M * d[o][l];
         }
     }
     return 0;
@@ -479,7 +541,8 @@ int oracle_init(const oracle_config *c, oracle_state *s)
     c8.order = 8;
     oracle_force(&c8, n, s->m, s->x, s->v, zero, zero, n, all, a, j, NULL, NULL, NULL);
     oracle_force(&c8, n, s->m, s->x, s->v, a, j, n, all, a2, j2, sn, cr, NULL);
-    oracle_pn(c, n, s->m, s->x, s->v, n, all, a, j);   /* hard pairs, when switched on */
+    /* hard pairs, when switched on (after pass 2, which used the Newtonian a, jerk) */
+    oracle_pn(c, n, s->m, s->x, s->v, n, all, a, j, p >= 6 ? sn : NULL, p >= 6 ? cr : NULL);
     /* pass 2 recomputes a and jerk identically (they do not depend on a, jerk);
      * the pass-1 values are the ones kept */
     memcpy(s->d[0], a, sizeof(double) * 3 * n);
@@ -542,7 +605,7 @@ int64_t oracle_block_step(const oracle_config *c, oracle_state *s, int64_t *t_ne
     double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n_act * 4);
     double *acc = F, *jrk = F + 3 * n_act, *snp = F + 6 * n_act, *crk = F + 9 * n_act;
     oracle_force(c, n, s->m, xp, vp, ap, jp, n_act, act, acc, jrk, snp, crk, NULL);
-    oracle_pn(c, n, s->m, xp, vp, n_act, act, acc, jrk);
+    oracle_pn(c, n, s->m, xp, vp, n_act, act, acc, jrk, p >= 6 ? snp : NULL, p >= 8 ? crk : NULL);
 
     int64_t under = 0, nonfinite = 0;
     int64_t qq;

@@ -62,7 +62,9 @@ def _load():
         lib.oracle_predict.argtypes = [C.POINTER(_Config), C.POINTER(_State), C.c_int64, P, P, P, P]
         lib.oracle_pn_rel.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P]
         lib.oracle_pn_rel.restype = None
-        lib.oracle_pn.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, P]
+        lib.oracle_pn_rel_derivs.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, P, P, P]
+        lib.oracle_pn_rel_derivs.restype = None
+        lib.oracle_pn.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, P, P, P]
         lib.oracle_force_nb.argtypes = [C.POINTER(_Config), C.c_int64, P, P, P, C.c_int64, P, P, C.c_int32,
                                         P, P, P, P, P, P]
         lib.oracle_hermite_high.argtypes = [C.c_int, C.c_double, P, P, P]
@@ -212,9 +214,21 @@ def pn_rel(M: float, nu: float, c: float, terms: int, x, v):
     return a, j
 
 
-def pn(cfg: OracleConfig, m, x, v, act, acc, jrk):
-    """Adds the post-Newtonian terms of the hard pairs to acc, jrk ((3, n_act)
-    arrays, modified in place) for the active list."""
+def pn_rel_derivs(M: float, nu: float, c: float, terms: int, x, v) -> np.ndarray:
+    """(4, 3): the post-Newtonian part of the two-body relative acceleration
+    and its first three time derivatives along the Newtonian two-body motion."""
+    lib = _load()
+    x = _f64(x, (3,))
+    v = _f64(v, (3,))
+    out = np.zeros((4, 3))
+    lib.oracle_pn_rel_derivs(float(M), float(nu), float(c), int(terms), _p(x), _p(v), _p(out))
+    return out
+
+
+def pn(cfg: OracleConfig, m, x, v, act, acc, jrk, snp=None, crk=None):
+    """Adds the post-Newtonian terms of the hard pairs to acc, jrk (and snp,
+    crk when given) ((3, n_act) arrays, modified in place) for the active
+    list."""
     lib = _load()
     m = _f64(m)
     n = m.shape[0]
@@ -222,7 +236,10 @@ def pn(cfg: OracleConfig, m, x, v, act, acc, jrk):
     v = _f64(v, (3, n))
     act = np.ascontiguousarray(act, np.int32)
     assert acc.dtype == np.float64 and acc.flags.c_contiguous and jrk.flags.c_contiguous
-    lib.oracle_pn(C.byref(cfg._c()), n, _p(m), _p(x), _p(v), act.shape[0], _p(act), _p(acc), _p(jrk))
+    for a in (snp, crk):
+        assert a is None or (a.dtype == np.float64 and a.flags.c_contiguous)
+    lib.oracle_pn(C.byref(cfg._c()), n, _p(m), _p(x), _p(v), act.shape[0], _p(act), _p(acc), _p(jrk), _p(snp),
+                  _p(crk))
 
 
 def predict(cfg: OracleConfig, s: State, t_tick: int):

@@ -10,8 +10,9 @@ two-body terms in harmonic coordinates) against results the physics fixes:
 * 1PN: the circular-orbit frequency omega^2 = (M/r^3)(1 - (3 - nu) M/(c^2 r)),
   and the periastron advance per orbit 6 pi M / (c^2 a (1 - e^2)) from
   Gauss' perturbation equation integrated over a Kepler orbit;
-* the jerk is the time derivative of the acceleration along the two-body
-  motion (central differences of the oracle's own acceleration);
+* the jerk, snap and crackle are the time derivatives of the acceleration
+  along the two-body motion (central differences of the oracle's own
+  acceleration on the integrated two-body path);
 * pairwise use conserves momentum and leaves soft particles alone;
 * the oracle's own block-step integration of a circular binary shrinks at
   Peters' rate.
@@ -127,6 +128,47 @@ def test_jerk_is_time_derivative_along_two_body_motion():
         am, _ = oracle.pn_rel(M, nu, c, 5, x - v * h + an * h * h / 2, v - an * h)
         fd = (ap - am) / (2 * h)
         np.testing.assert_allclose(j, fd, rtol=1e-6, atol=1e-9 * np.abs(j).max())
+
+
+def _two_body_path(M, x, v, ts, substeps=200):
+    """States (x, v) of the Newtonian two-body motion at the times ts (RK4
+    from t = 0 in small steps, forward and backward)."""
+    def f(y):
+        r = y[:3]
+        return np.concatenate([y[3:], -M * r / np.linalg.norm(r) ** 3])
+    out = []
+    for t in ts:
+        y = np.concatenate([x, v]).astype(float)
+        h = t / substeps
+        for _ in range(substeps):
+            k1 = f(y); k2 = f(y + h / 2 * k1); k3 = f(y + h / 2 * k2); k4 = f(y + h * k3)
+            y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        out.append((y[:3], y[3:]))
+    return out
+
+
+def test_snap_and_crackle_are_time_derivatives_along_two_body_motion():
+    """Second and third derivatives of the oracle's own PN acceleration along
+    the integrated two-body path (central differences) equal its snap and
+    crackle; its jerk and acceleration agree with the first-derivative route."""
+    rng = np.random.default_rng(33)
+    for _ in range(4):
+        M, nu, c = rng.uniform(0.5, 2.0), rng.uniform(0.05, 0.25), rng.uniform(5.0, 20.0)
+        x = rng.normal(size=3)
+        v = rng.normal(size=3) * np.sqrt(M / np.linalg.norm(x))
+        d = oracle.pn_rel_derivs(M, nu, c, 5, x, v)
+        a, j = oracle.pn_rel(M, nu, c, 5, x, v)
+        np.testing.assert_array_equal(d[0], a)
+        np.testing.assert_array_equal(d[1], j)
+        h = 2e-3
+        f = {k: oracle.pn_rel(M, nu, c, 5, xs, vs)[0]
+             for k, (xs, vs) in zip((-2, -1, 1, 2), _two_body_path(M, x, v, (-2 * h, -h, h, 2 * h)))}
+        f[0] = a
+        snap = (f[1] - 2 * f[0] + f[-1]) / h ** 2
+        crackle = (f[2] - 2 * f[1] + 2 * f[-1] - f[-2]) / (2 * h ** 3)
+        scale_s, scale_c = np.abs(d[2]).max(), np.abs(d[3]).max()
+        np.testing.assert_allclose(d[2], snap, rtol=0, atol=2e-5 * scale_s)
+        np.testing.assert_allclose(d[3], crackle, rtol=0, atol=2e-4 * scale_c)
 
 
 def test_pairwise_terms_conserve_momentum_and_skip_soft_particles():
