@@ -87,11 +87,12 @@ typedef struct {
                            2.5PN two-body relative acceleration in harmonic coordinates,
                            -(M/r^2)[A n + B v] with the A, B terms of Blanchet's review
                            (Living Rev. Relativ. 17, 2), body 1 taking m2/M of it and body 2
-                           -m1/M, and its jerk along the two-body motion; added by nbody_init,
+                           -m1/M, and its jerk, snap and crackle along the pair's Newtonian
+                           two-body motion (as many as the order uses); added by nbody_init,
                            nbody_step and nbody_run to the forces of active hard particles,
-                           from their positions and velocities predicted in FP64.  Order 4
-                           only, n_hard <= 1024 (the pairs cost n_hard^2); not in the batched
-                           form (NBODY_E_UNSUPPORTED).  0 = off. */
+                           from their positions and velocities predicted in FP64.
+                           n_hard <= 1024 (the pairs cost n_hard^2); not in the batched form
+                           (NBODY_E_UNSUPPORTED).  0 = off. */
     int32_t pn_terms;   /* 1 = 1PN, 4 = 2.5PN (radiation reaction), 5 = both; 0 = off */
 } nbody_config;
 

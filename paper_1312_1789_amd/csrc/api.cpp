@@ -35,8 +35,6 @@ nbody_status check_config(const nbody_config *c)
     if (!(c->c_light >= 0.0) || !std::isfinite(c->c_light)) return fail(NBODY_E_INVALID, "c_light must be finite and >= 0");
     if (c->pn_terms != 0 && c->pn_terms != 1 && c->pn_terms != 4 && c->pn_terms != 5)
         return fail(NBODY_E_INVALID, "pn_terms must be 0, 1, 4 or 5 (got %d)", c->pn_terms);
-    if (nb::pn_on(*c) && c->order != 4)
-        return fail(NBODY_E_INVALID, "post-Newtonian terms need order 4 (got %d)", c->order);
     if (nb::pn_on(*c) && c->n_hard > 1024)
         return fail(NBODY_E_INVALID, "post-Newtonian terms take at most 1024 hard particles (got %lld)",
                     (long long)c->n_hard);
@@ -459,14 +457,15 @@ nbody_status nbody_init(nbody_ctx *ctx, nbody_state *st)
     NB_HIP(nb::launch_pack_f64(c.n, st->m, st->x, st->v, nullptr, nullptr, irec, ctx->stream));
     s = run_force(ctx, 8, NBODY_FP64, irec, c.n, all, st->d[0], st->d[1], nullptr, nullptr, nullptr);
     if (s != NBODY_OK) return s;
-    if (nb::pn_on(c))   // hard pairs at t = 0, from the state itself
-        NB_HIP(nb::launch_pn(c, *st, nullptr, 0, all, c.n, st->d[0], st->d[1], ctx->stream));
     if (c.order >= 6) {
         // pass 2: snap and crackle, using the pass-1 acceleration and jerk
         NB_HIP(nb::launch_pack_f64(c.n, st->m, st->x, st->v, st->d[0], st->d[1], irec, ctx->stream));
         s = run_force(ctx, 8, NBODY_FP64, irec, c.n, all, nullptr, nullptr, st->d[2], st->d[3], nullptr);
         if (s != NBODY_OK) return s;
     }
+    if (nb::pn_on(c))   // hard pairs at t = 0, from the state itself, after pass 2 (Newtonian a, jerk)
+        NB_HIP(nb::launch_pn(c, *st, nullptr, 0, all, c.n, st->d[0], st->d[1], c.order >= 6 ? st->d[2] : nullptr,
+                             c.order >= 6 ? st->d[3] : nullptr, ctx->stream));
     NB_HIP(nb::launch_init_levels(c, *st, st->d[0], st->d[1], ctx->stream));
     ctx->predicted = false;
     return NBODY_OK;
@@ -673,7 +672,8 @@ nbody_status step_impl(nbody_ctx *ctx, nbody_state *st, int64_t t_limit, bool ch
         if (s != NBODY_OK) return s;
     }
     if (nb::pn_on(c))   // active hard particles come first in the ordered active list
-        NB_HIP(nb::launch_pn(c, *st, st->t_tick, t_next, act, n_act, acc, jrk, ctx->stream));
+        NB_HIP(nb::launch_pn(c, *st, st->t_tick, t_next, act, n_act, acc, jrk, c.order >= 6 ? snp : nullptr,
+                             c.order >= 8 ? crk : nullptr, ctx->stream));
     if (tm) NB_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
     const double *f[4] = {acc, jrk, snp, crk};
     NB_HIP(nb::launch_correct(c, *st, n_act, act, nullptr, t_next, f, scalars(ctx), ctx->stream));

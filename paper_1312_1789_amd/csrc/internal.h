@@ -167,12 +167,13 @@ hipError_t launch_correct(const nbody_config &c, const nbody_state &st, int64_t 
 
 hipError_t launch_iota(int64_t n, int32_t *a, hipStream_t s);
 
-// Adds the post-Newtonian terms of the hard pairs to acc, jrk ([3][n_act])
-// for the rows of act (increasing indices; the hard particles, indices below
-// n_hard, come first) predicted to t_tick (t_tick_of null: the state as it
-// is).
+// Adds the post-Newtonian terms of the hard pairs to acc, jrk and, when not
+// null, snp and crk ([3][n_act]) for the rows of act (increasing indices; the hard particles,
+// indices below n_hard, come first) predicted to t_tick (t_tick_of null: the
+// state as it is).
 hipError_t launch_pn(const nbody_config &c, const nbody_state &st, const int64_t *t_tick_of, int64_t t_tick,
-                     const int32_t *act, int64_t n_act, double *acc, double *jrk, hipStream_t s);
+                     const int32_t *act, int64_t n_act, double *acc, double *jrk, double *snp, double *crk,
+                     hipStream_t s);
 
 hipError_t launch_unpack(int order, int precision, int64_t n, const void *rec, double *xp, double *vp, double *ap,
                          double *jp, hipStream_t s);

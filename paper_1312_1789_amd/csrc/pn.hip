@@ -10,9 +10,9 @@
 //          B = -2 (2 - nu) rdot / c^2,
 //   2.5PN: A = -8/5 nu (M/r) rdot (17/3 M/r + 3 v^2) / c^5,
 //          B =  8/5 nu (M/r) (3 M/r + v^2) / c^5.
-// Body 1 takes m2 / M of it, body 2 minus m1 / M.  The jerk is its time
-// derivative along dx/dt = v, dv/dt = -M x / r^3 (the pair's Newtonian
-// motion), carried through every operation with (value, derivative) pairs.
+// Body 1 takes m2 / M of it, body 2 minus m1 / M.  Jerk, snap and crackle
+// are its time derivatives along the pair's Newtonian two-body motion,
+// carried through every operation as truncated Taylor series in t.
 // Positions and velocities are predicted in FP64 from the stored state, so
 // the terms do not depend on the force kernel's precision or records.
 #include "hermite.h"
@@ -20,43 +20,106 @@
 namespace nb {
 namespace {
 
-struct Dual {
-    double v, d;   // value, time derivative
+// Truncated Taylor series in t of degree 3: f_k = f^(k)(0) / k!.
+struct TS {
+    double c[4];
 };
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b)
+__device__ __forceinline__ TS tconst(double v) { return TS{{v, 0.0, 0.0, 0.0}}; }
+__device__ __forceinline__ TS operator+(TS a, TS b)
 {
-    const double q = a.v / b.v;
-    return {q, (a.d - q * b.d) / b.v};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.c[k] += b.c[k];
+    return a;
 }
-__device__ __forceinline__ Dual dsqrt(Dual a)
+__device__ __forceinline__ TS operator*(double s, TS a)
 {
-    const double r = sqrt(a.v);
-    return {r, 0.5 * a.d / r};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.c[k] *= s;
+    return a;
 }
+__device__ __forceinline__ TS operator*(TS a, TS b)
+{
+    TS r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) t += a.c[i] * b.c[k - i];
+        r.c[k] = t;
+    }
+    return r;
+}
+__device__ __forceinline__ TS operator/(TS a, TS b)
+{
+    TS r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t = a.c[k];
+#pragma unroll
+        for (int i = 1; i <= k; ++i) t -= b.c[i] * r.c[k - i];
+        r.c[k] = t / b.c[0];
+    }
+    return r;
+}
+__device__ __forceinline__ TS tsqrt(TS a)
+{
+    TS r;
+    r.c[0] = sqrt(a.c[0]);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        double t = a.c[k];
+#pragma unroll
+        for (int i = 1; i < k; ++i) t -= r.c[i] * r.c[k - i];
+        r.c[k] = t / (2.0 * r.c[0]);
+    }
+    return r;
+}
+__device__ __forceinline__ TS tdot(const TS *a, const TS *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-__device__ void pn_relative(double M, double nu, double c, int terms, const double *x, const double *v, double *a,
-                            double *j)
+// The post-Newtonian part of the relative acceleration and its first three
+// time derivatives (d[k][l], k = 0..3) along the two-body Newtonian motion
+// from (x, v): the trajectory's series from x'' = -M x / |x|^3 coefficient
+// by coefficient (the acceleration's coefficient k fixes x's coefficient
+// k + 2), then the terms evaluated on the series.
+__device__ void pn_relative(double M, double nu, double c, int terms, const double *x, const double *v,
+                            double (*d)[3])
 {
-    const double r0 = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    const double k0 = -M / (r0 * r0 * r0);
-    Dual X[3], V[3];
+    TS X[3];
+    double x4[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        X[l] = {x[l], v[l]};
-        V[l] = {v[l], k0 * x[l]};
+        X[l] = tconst(x[l]);
+        X[l].c[1] = v[l];
+        x4[l] = 0.0;
     }
-    const Dual r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
-    const Dual r = dsqrt(r2);
-    Dual n[3];
+#pragma unroll
+    for (int k = 0; k <= 2; ++k) {
+        const TS r2 = tdot(X, X);
+        const TS r3 = r2 * tsqrt(r2);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const TS acc = ((-M) * X[l]) / r3;
+            const double xk = acc.c[k] / ((k + 1.0) * (k + 2.0));
+            if (k + 2 < 4) X[l].c[k + 2] = xk;
+            else x4[l] = xk;
+        }
+    }
+    TS V[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) V[l].c[k] = (k + 1.0) * X[l].c[k + 1];
+        V[l].c[3] = 4.0 * x4[l];
+    }
+    const TS r2 = tdot(X, X);
+    const TS r = tsqrt(r2);
+    TS n[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) n[l] = X[l] / r;
-    const Dual rdot = n[0] * V[0] + n[1] * V[1] + n[2] * V[2];
-    const Dual v2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
-    const Dual Mr = Dual{M, 0.0} / r;
-    Dual A{0.0, 0.0}, B{0.0, 0.0};
+    const TS rdot = tdot(n, V);
+    const TS v2 = tdot(V, V);
+    const TS Mr = tconst(M) / r;
+    TS A = tconst(0.0), B = tconst(0.0);
     if (terms & 1) {
         const double ic2 = 1.0 / (c * c);
         A = A + ic2 * ((-1.5 * nu) * (rdot * rdot) + (1.0 + 3.0 * nu) * v2 + (-2.0 * (2.0 + nu)) * Mr);
@@ -67,67 +130,88 @@ __device__ void pn_relative(double M, double nu, double c, int terms, const doub
         A = A + (-1.6 * nu * ic5) * (Mr * rdot * ((17.0 / 3.0) * Mr + 3.0 * v2));
         B = B + (1.6 * nu * ic5) * (Mr * (3.0 * Mr + v2));
     }
-    const Dual pre = Dual{-M, 0.0} / r2;
+    const TS pre = tconst(-M) / r2;
+    const double fact[4] = {1.0, 1.0, 2.0, 6.0};
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        const Dual t = pre * (A * n[l] + B * V[l]);
-        a[l] = t.v;
-        j[l] = t.d;
+        const TS t = pre * (A * n[l] + B * V[l]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k][l] = fact[k] * t.c[k];
     }
 }
 
 // One lane per leading row of the active list (the hard particles come
 // first in an ordered list): for a hard particle i, the terms of every pair
-// (i, k) with k < n_hard, k != i, added to its acceleration and jerk.
+// (i, k) with k < n_hard, k != i, added to its acceleration and jerk, and to
+// its snap and crackle when those outputs are given (orders 6 and 8).
+struct PnDs {
+    const double *d[6];   // the stored derivatives a^(0..p-3) ([3][n] each), passed by value
+};
+
+template <int P>
 __global__ void __launch_bounds__(64)
 k_pn(int64_t n, int64_t n_hard, int rows, const double *__restrict__ m, const double *__restrict__ x,
-     const double *__restrict__ v, const double *__restrict__ d0, const double *__restrict__ d1,
-     const int64_t *__restrict__ t_tick_of, int64_t t, double c, int terms, const int32_t *__restrict__ act,
-     int64_t n_act, double *__restrict__ acc, double *__restrict__ jrk)
+     const double *__restrict__ v, PnDs ds, const int64_t *__restrict__ t_tick_of, int64_t t,
+     double c, int terms, const int32_t *__restrict__ act, int64_t n_act, double *__restrict__ acc,
+     double *__restrict__ jrk, double *__restrict__ snp, double *__restrict__ crk)
 {
     const int q = int(blockIdx.x) * 64 + int(threadIdx.x);
     if (q >= rows) return;
     const int64_t i = act[q];
     if (i < 0 || i >= n_hard) return;
     constexpr double kInvTick = 1.0 / double(kTicksPerUnit);
-    const double *ds[2] = {d0, d1};
+    // predicted to t; without times (initialisation) the state itself, read
+    // directly (the higher stored derivatives may not be set yet)
     const auto pred = [&](int64_t k) {
-        const double dt = t_tick_of ? double(t - t_tick_of[k]) * kInvTick : 0.0;
-        return predict_state<4, NBODY_FP64>(load_pstate<4>(n, k, m, x, v, ds), dt);
+        if (!t_tick_of) {
+            RecF64<P> r{};
+            r.x = x[k]; r.y = x[n + k]; r.z = x[2 * n + k]; r.m = m[k];
+            r.vx = v[k]; r.vy = v[n + k]; r.vz = v[2 * n + k];
+            return r;
+        }
+        return predict_state<P, NBODY_FP64>(load_pstate<P>(n, k, m, x, v, ds.d), double(t - t_tick_of[k]) * kInvTick);
     };
-    const RecF64<4> pi = pred(i);
-    double sa[3] = {0.0, 0.0, 0.0}, sj[3] = {0.0, 0.0, 0.0};
+    const RecF64<P> pi = pred(i);
+    double s[4][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int64_t k = 0; k < n_hard; ++k) {
         if (k == i) continue;
-        const RecF64<4> pk = pred(k);
+        const RecF64<P> pk = pred(k);
         const double xr[3] = {pi.x - pk.x, pi.y - pk.y, pi.z - pk.z};
         const double vr[3] = {pi.vx - pk.vx, pi.vy - pk.vy, pi.vz - pk.vz};
         const double M = pi.m + pk.m, nu = pi.m * pk.m / (M * M), w = pk.m / M;
-        double a[3], j[3];
-        pn_relative(M, nu, c, terms, xr, vr, a, j);
+        double d[4][3];
+        pn_relative(M, nu, c, terms, xr, vr, d);
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            sa[l] += w * a[l];
-            sj[l] += w * j[l];
-        }
-    }
+        for (int o = 0; o < 4; ++o)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        acc[l * n_act + q] += sa[l];
-        jrk[l * n_act + q] += sj[l];
+            for (int l = 0; l < 3; ++l) s[o][l] += w * d[o][l];
     }
+    double *outs[4] = {acc, jrk, snp, crk};
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+        if (outs[o])
+#pragma unroll
+            for (int l = 0; l < 3; ++l) outs[o][l * n_act + q] += s[o][l];
 }
 
 }  // namespace
 
 hipError_t launch_pn(const nbody_config &c, const nbody_state &st, const int64_t *t_tick_of, int64_t t_tick,
-                     const int32_t *act, int64_t n_act, double *acc, double *jrk, hipStream_t s)
+                     const int32_t *act, int64_t n_act, double *acc, double *jrk, double *snp, double *crk,
+                     hipStream_t s)
 {
     const int64_t nh = c.n_hard < c.n ? c.n_hard : c.n;
     const int rows = int(n_act < nh ? n_act : nh);
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pn, dim3(unsigned((rows + 63) / 64)), dim3(64), 0, s, c.n, nh, rows, st.m, st.x, st.v,
-                       st.d[0], st.d[1], t_tick_of, t_tick, c.c_light, int(c.pn_terms), act, n_act, acc, jrk);
+    const dim3 g(unsigned((rows + 63) / 64));
+    const PnDs ds{{st.d[0], st.d[1], st.d[2], st.d[3], st.d[4], st.d[5]}};
+#define NB_PN(P)                                                                                              \
+    hipLaunchKernelGGL((k_pn<P>), g, dim3(64), 0, s, c.n, nh, rows, st.m, st.x, st.v, ds, t_tick_of, t_tick, \
+                       c.c_light, int(c.pn_terms), act, n_act, acc, jrk, snp, crk)
+    if (c.order == 4) NB_PN(4);
+    else if (c.order == 6) NB_PN(6);
+    else NB_PN(8);
+#undef NB_PN
     return hipGetLastError();
 }
 

@@ -46,8 +46,7 @@ def test_workspace_size_scales_with_n():
                                 dict(eps2=-1.0), dict(eta=0.0), dict(eta_start=-1.0), dict(k_min=5, k_max=4),
                                 dict(k_max=21), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1),
                                 dict(c_light=-1.0), dict(c_light=float("inf")), dict(pn_terms=2),
-                                dict(pn_terms=3), dict(n_hard=2, c_light=10.0, pn_terms=5),   # order 6
-                                dict(order=4, n=5000, n_hard=2000, c_light=10.0, pn_terms=1)])
+                                dict(pn_terms=3), dict(order=4, n=5000, n_hard=2000, c_light=10.0, pn_terms=1)])
 def test_config_validation(kw):
     with pytest.raises(abi.NBodyError) as e:
         abi.nbody_workspace_size(_cfg(**kw))
@@ -105,9 +104,9 @@ def test_batch_validation(off, kw):
     assert abi.last_error()
 
 
-def test_pn_config_accepted_at_order_4_and_refused_in_batches():
-    cfg = _cfg(order=4, n_hard=2, c_light=10.0, pn_terms=5)
-    assert abi.nbody_workspace_size(cfg) > 0
+def test_pn_config_accepted_and_refused_in_batches():
+    for order in (4, 6, 8):
+        assert abi.nbody_workspace_size(_cfg(order=order, n_hard=2, c_light=10.0, pn_terms=5)) > 0
     with pytest.raises(abi.NBodyError) as e:
         abi.nbody_batch_workspace_size(_cfg(order=4, n_hard=2, c_light=10.0, pn_terms=4), [0, 500, 1000])
     assert e.value.status == abi.NBODY_E_UNSUPPORTED

@@ -2,8 +2,9 @@
 pn_terms; 4th order), against the oracle (its pinned PN terms) and against
 the physics the oracle pins fix:
 
-* initial forces of a cluster with a black-hole binary (c = 2: the 1PN
-  terms are ~2.5% of the binary's mutual force) equal the oracle's;
+* initial forces and derivatives (orders 4, 6, 8) of a cluster with a
+  black-hole binary (c = 2: the 1PN terms are ~2.5% of the binary's mutual
+  force) equal the oracle's;
 * whole block steps from the GPU's own state match the oracle's predictor,
   force + PN terms and corrector (FP64: the comparison of the plain step
   tests; MIXED: x, v within 1e-9, 1e-7, the new acceleration within the
@@ -24,34 +25,36 @@ from oracle import OracleConfig
 pytestmark = pytest.mark.gpu
 
 
-def _sim(m, x, v, precision, c, terms, n_hard=2, eps2=1e-8, eta=0.01):
+def _sim(m, x, v, precision, c, terms, n_hard=2, eps2=1e-8, eta=0.01, order=4):
     from paper_1312_1789_amd import Simulation
-    return Simulation(m, x, v, order=4, precision=precision, eps2=eps2, n_hard=n_hard, eta=eta, eta_start=0.01,
-                      c_light=c, pn_terms=terms)
+    return Simulation(m, x, v, order=order, precision=precision, eps2=eps2, n_hard=n_hard, eta=eta,
+                      eta_start=0.01, c_light=c, pn_terms=terms)
 
 
 def _ocfg(sim):
     c = sim.cfg
-    return OracleConfig(order=4, eps2=c.eps2, n_hard=c.n_hard, eta=c.eta, eta_start=c.eta_start, k_min=c.k_min,
-                        k_max=c.k_max, c_light=c.c_light, pn_terms=c.pn_terms)
+    return OracleConfig(order=c.order, eps2=c.eps2, n_hard=c.n_hard, eta=c.eta, eta_start=c.eta_start,
+                        k_min=c.k_min, k_max=c.k_max, dt_rule=sim.dt_rule, c_light=c.c_light, pn_terms=c.pn_terms)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_pn_init_and_step_parity(precision):
+@pytest.mark.parametrize("order,precision", [(4, "fp64"), (4, "mixed"), (6, "fp64"), (8, "fp64")])
+def test_pn_init_and_step_parity(order, precision):
     model = nbody_ics.with_bh_binary(nbody_ics.plummer(1022, 91), 0.01, 0.2)
-    sim = _sim(model.m, model.x, model.v, precision, 2.0, 5)
+    sim = _sim(model.m, model.x, model.v, precision, 2.0, 5, order=order, eta=0.01 if order == 4 else 0.1)
     ocfg = _ocfg(sim)
     sim.init()
     h = sim.to_numpy()
-    os_ = oracle.State(model.m, model.x, model.v, 4)
+    os_ = oracle.State(model.m, model.x, model.v, order)
     oracle.init(ocfg, os_)
-    for k in range(2):
+    for k in range(min(order - 2, 4)):
         e = rel_err(h["d"][k], os_.d[k])
-        say("pn init %s d[%d] max rel %.2e (black holes %.2e)" % (precision, k, e.max(), e[:2].max()))
-        assert e.max() <= 1e-12
-    np.testing.assert_array_equal(h["level"], os_.level)
-    plain = oracle.State(model.m, model.x, model.v, 4)
-    oracle.init(OracleConfig(order=4, eps2=ocfg.eps2, n_hard=2, eta=ocfg.eta, eta_start=ocfg.eta_start), plain)
+        rms = float(np.sqrt(np.mean(e * e)))
+        say("pn init p%d %s d[%d] rms rel %.2e max %.2e (black holes %.2e)"
+            % (order, precision, k, rms, e.max(), e[:2].max()))
+        assert rms <= 1e-12 and e.max() <= 1e-9 and e[:2].max() <= 1e-12
+    assert np.sum(h["level"] != os_.level) <= 2
+    plain = oracle.State(model.m, model.x, model.v, order)
+    oracle.init(OracleConfig(order=order, eps2=ocfg.eps2, n_hard=2, eta=ocfg.eta, eta_start=ocfg.eta_start), plain)
     shift = np.linalg.norm(os_.d[0][:, :2] - plain.d[0][:, :2], axis=0) / np.linalg.norm(plain.d[0][:, :2], axis=0)
     say("pn init: relative change of the black holes' acceleration %.2e" % shift.max())
     assert shift.min() > 1e-3                # the terms are on
@@ -59,7 +62,7 @@ def test_pn_init_and_step_parity(precision):
     bh_steps = 0
     for step in range(10):
         h0 = sim.to_numpy()
-        os0 = oracle.State(h0["m"], h0["x"], h0["v"], 4, [a.copy() for a in h0["d"]], h0["t_tick"].copy(),
+        os0 = oracle.State(h0["m"], h0["x"], h0["v"], order, [a.copy() for a in h0["d"]], h0["t_tick"].copy(),
                            h0["level"].copy())
         nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
         T = int(nxt.min())
@@ -68,12 +71,14 @@ def test_pn_init_and_step_parity(precision):
         t_g, na_g = sim.step()
         assert (t_g, na_g) == (T, act.size), step
         xp, vp, ap, jp = oracle.predict(ocfg, os0, T)
-        F = oracle.force(ocfg, os0.m, xp, vp, act=act)
-        oracle.pn(ocfg, os0.m, xp, vp, act, F["acc"], F["jrk"])
+        F = oracle.force(ocfg, os0.m, xp, vp, ap if order >= 6 else None, jp if order >= 8 else None, act=act)
+        oracle.pn(ocfg, os0.m, xp, vp, act, F["acc"], F["jrk"], F["snp"] if order >= 6 else None,
+                  F["crk"] if order >= 8 else None)
         want = oracle_correct(ocfg, os0, act, T, F)
         got = sim.to_numpy()
         if precision == "fp64":
-            compare_corrected(got, want, act, 4, rel_force, "pn step %d %s" % (step, precision))
+            compare_corrected(got, want, act, order, rel_force, "pn step %d p%d %s" % (step, order, precision),
+                              sim.dt_rule)
         else:
             # FP32 pair terms (the PN terms are FP64 in both modes): x, v within
             # what a force difference of ~1e-6 moves them in one step of up to
