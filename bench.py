@@ -789,8 +789,17 @@ def run_c3(args):
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.c3_c > 0:
+        sim, relat = integrate_run(model, "c3, post-Newtonian", t_end, hist_pass=False, c_light=args.c3_c,
+                                   pn_terms=5, **kw)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
     sim, rec = integrate_run(model, "c3", t_end, hist_pass=False, **kw)
     rec["without_fusion"] = {k: plain[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
+    if args.c3_c > 0:
+        rec["post_newtonian"] = {k: relat[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
+        rec["post_newtonian"]["c_light"] = args.c3_c
     h = sim.to_numpy()
     sep0 = float(np.linalg.norm(x0[:, 0] - x0[:, 1]))
     sep1 = float(np.linalg.norm(h["x"][:, 0] - h["x"][:, 1]))
@@ -816,6 +825,7 @@ def main():
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
     ap.add_argument("--c3-t-end", type=float, default=1.0 / 256)
+    ap.add_argument("--c3-c", type=float, default=0.0, help="c3: also run with 1PN + 2.5PN terms at this c")
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")
     ap.add_argument("--small-n", default="131072,1048576", help="smallstep: particle counts")
