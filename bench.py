@@ -585,6 +585,29 @@ def run_neighbour(args):
     print(json.dumps(line), flush=True)
 
 
+def binary_gw(h, c, i=0, j=1):
+    """Diagnostics of the pair (i, j) from a to_numpy() state: Newtonian
+    relative-orbit semi-major axis a and eccentricity e, Peters' (1964)
+    orbit-averaged gravitational-wave luminosity (32/5) nu^2 M^5 / (a^5 c^5)
+    (1 + 73/24 e^2 + 37/96 e^4) / (1 - e^2)^(7/2) and his circular-orbit
+    inspiral time (5/256) a^4 c^5 / (nu M^3) (G = 1)."""
+    m1, m2 = h["m"][i], h["m"][j]
+    M = m1 + m2
+    nu = m1 * m2 / (M * M)
+    r = h["x"][:, i] - h["x"][:, j]
+    w = h["v"][:, i] - h["v"][:, j]
+    rn = np.linalg.norm(r)
+    a = -M / (2.0 * (0.5 * np.dot(w, w) - M / rn))
+    ecc = np.linalg.norm(np.cross(w, np.cross(r, w)) / M - r / rn)
+    e2 = ecc * ecc
+    out = {"a": float(a), "e": float(ecc)}
+    if c > 0 and a > 0 and e2 < 1:
+        out["gw_luminosity"] = float(32.0 / 5.0 * nu ** 2 * M ** 5 / (a ** 5 * c ** 5)
+                                     * (1 + 73.0 / 24.0 * e2 + 37.0 / 96.0 * e2 * e2) / (1 - e2) ** 3.5)
+        out["inspiral_time_circular"] = float(5.0 / 256.0 * a ** 4 * c ** 5 / (nu * M ** 3))
+    return out
+
+
 def run_pn(args):
     """Block steps of a cluster with a black-hole binary with and without the
     post-Newtonian terms of the binary (4th order, MIXED): whole-step rate,
@@ -617,9 +640,12 @@ def run_pn(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st = sim.stats()
-        a1 = binary_a(sim.to_numpy())
+        h_end = sim.to_numpy()
+        a1 = binary_a(h_end)
         runs[label] = {"steps": steps, "wall_s": wall, "interactions_per_s": st.interactions / wall,
-                       "ms_per_step": wall / max(steps, 1) * 1e3, "binary_a": [a0, a1]}
+                       "ms_per_step": wall / max(steps, 1) * 1e3, "binary_a": [a0, a1],
+                       "binary_end": binary_gw(h_end, args.pn_c)}
+        log("[pn] %-9s binary at the end: %s" % (label, runs[label]["binary_end"]))
         log("[pn] %-9s %d steps to t = %.5f in %.2f s (%.3f ms/step, %.3e int/s); binary a %.6f -> %.6f"
             % (label, steps, t_end / 2.0 ** 20, wall, runs[label]["ms_per_step"], runs[label]["interactions_per_s"],
                a0, a1))
@@ -804,7 +830,8 @@ def run_c3(args):
     sep0 = float(np.linalg.norm(x0[:, 0] - x0[:, 1]))
     sep1 = float(np.linalg.norm(h["x"][:, 0] - h["x"][:, 1]))
     rec["bh_separation"] = [sep0, sep1]
-    log("[c3] BH separation %.6f -> %.6f" % (sep0, sep1))
+    rec["bh_binary_end"] = binary_gw(h, args.c3_c)
+    log("[c3] BH separation %.6f -> %.6f; binary at the end %s" % (sep0, sep1, rec["bh_binary_end"]))
     line = {
         "metric": "C3: whole-run pair interactions/s, King W0=7 2^20 stars + BH binary, 8th order, MIXED",
         "value": rec["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1, "steps": rec["steps"],
