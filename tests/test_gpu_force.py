@@ -183,7 +183,8 @@ def test_force_max_size_sampled():
     4096 random active rows through the tiled kernels and 7 through the wave
     j-split kernel, in FP64 and MIXED; 128 and 7 rows checked against the
     oracle (64-bit indexing, split-count and partial-buffer caps at full
-    size)."""
+    size); the 7 rows again with the predictor inside the kernel, bit for
+    bit."""
     n = 1 << 26
     model = nbody_ics.plummer(n, 1717)
     d = random_derivs(n, 1718, 4)
@@ -203,11 +204,16 @@ def test_force_max_size_sampled():
             say("   %-6s %-4s rms %.2e max %.2e" % (precision, key, st["rms"], st["max"]))
             tol = FP64_TOL["rms"] if precision == "fp64" else LOW_TOL[key]
             assert st["rms"] <= tol, (key, st)
-        out = sim.force_block(torch.as_tensor(tiny, device=sim.device), with_pot=False)
+        tiny_t = torch.as_tensor(tiny, device=sim.device)
+        out = sim.force_block(tiny_t, with_pot=False)
         for key in ("acc", "jrk"):
             e = rel_err(out[key].cpu().numpy(), ref_tiny[key])
             say("   %-6s %-4s (7 rows, wave j-split) max %.2e" % (precision, key, float(e.max())))
             assert float(e.max()) <= (FP64_TOL["max"] if precision == "fp64" else 20 * LOW_TOL[key]), key
+        # the same rows with the predictor inside the force kernel: the same bits
+        fused = sim.predict_force(5 * (TICKS >> 3), tiny_t, with_pot=False)
+        for key in ("acc", "jrk"):
+            assert torch.equal(fused[key], out[key]), key
         sim.close()
         del sim, out
         torch.cuda.empty_cache()
