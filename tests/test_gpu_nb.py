@@ -202,3 +202,27 @@ def test_nb_validation():
     out = sim.force_block_nb(act, h2, 8)
     assert torch.isfinite(out["acc_reg"]).all()
     sim.close()
+
+
+def test_nb_max_size_sampled():
+    """The largest system the C-ABI accepts, n = 2^26 (Plummer): 512 active
+    rows, 3 of them with radii in distance gaps checked against the oracle
+    (64-bit indexing of the lists and partial sums at full size), FP64 and
+    MIXED."""
+    n = 1 << 26
+    model = nbody_ics.plummer(n, 89)
+    act = nbody_ics.active_subset(n, 512, 90)
+    check = np.array([0, 255, 511])
+    h2 = np.full(act.size, 1e-9)
+    h2c, margin = band_free_radii(model.x, act[check], 91, k_max=30)
+    h2[check] = h2c
+    ref = oracle.force_nb(OracleConfig(order=4, eps2=1e-8), model.m, model.x, model.v, act[check], h2c, 64)
+    for precision in ("fp64", "mixed"):
+        say("max-size neighbour split %s n=%d" % (precision, n))
+        sim = _sim(model, precision, 1e-8, 0)
+        got = _run(sim, act, h2, 64)
+        sub = {k: (v[:, check] if k in PARTS else v[check]) for k, v in got.items()}
+        _compare(sub, ref, check.size, 64, precision, "2^26")
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
