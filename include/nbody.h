@@ -156,7 +156,9 @@ nbody_status nbody_predict(nbody_ctx *ctx, const nbody_state *state, int64_t t_t
  * act_idx: int32 indices in [0, n), no duplicates (order free).
  * Outputs [3][n_act] (pot: [n_act]) FP64, row q belongs to act_idx[q].
  * snp / crk may be NULL when the order does not define them; pot may be
- * NULL.  The j-sum order is fixed, so reruns are bitwise identical. */
+ * NULL.  The j-sum order is fixed, so reruns are bitwise identical.
+ * Newtonian force only: the post-Newtonian terms of a context with c_light
+ * set are added by nbody_init, nbody_step and nbody_run, not here. */
 nbody_status nbody_force_block(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, double *acc,
                                double *jrk, double *snp, double *crk, double *pot);
 

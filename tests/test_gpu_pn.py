@@ -4,7 +4,7 @@ the physics the oracle pins fix:
 
 * initial forces and derivatives (orders 4, 6, 8) of a cluster with a
   black-hole binary (c = 2: the 1PN terms are ~2.5% of the binary's mutual
-  force) equal the oracle's;
+  force), and with a third black hole (three pairs), equal the oracle's;
 * whole block steps from the GPU's own state match the oracle's predictor,
   force + PN terms and corrector (FP64: the comparison of the plain step
   tests; MIXED: x, v within 1e-9, 1e-7, the new acceleration within the
@@ -37,10 +37,27 @@ def _ocfg(sim):
                         k_min=c.k_min, k_max=c.k_max, dt_rule=sim.dt_rule, c_light=c.c_light, pn_terms=c.pn_terms)
 
 
-@pytest.mark.parametrize("order,precision", [(4, "fp64"), (4, "mixed"), (6, "fp64"), (8, "fp64")])
-def test_pn_init_and_step_parity(order, precision):
+def _bh_model(n_bh):
+    """Plummer cluster with a black-hole binary (indices 0, 1; separation 0.2,
+    mass 0.01 each) and, for n_bh = 3, a third black hole of the same mass at
+    index 2 on a roughly circular orbit about the binary at distance 0.2
+    (three pairs of post-Newtonian terms per hard particle row)."""
     model = nbody_ics.with_bh_binary(nbody_ics.plummer(1022, 91), 0.01, 0.2)
-    sim = _sim(model.m, model.x, model.v, precision, 2.0, 5, order=order, eta=0.01 if order == 4 else 0.1)
+    if n_bh == 3:
+        m, x, v = model.m.copy(), model.x.copy(), model.v.copy()
+        m[2] = 0.01
+        x[:, 2] = [0.0, 0.16, 0.12]
+        v[:, 2] = np.array([-1.0, 0.0, 0.0]) * np.sqrt(0.02 / 0.2)
+        model = nbody_ics.Model(m, x, v)
+    return model
+
+
+@pytest.mark.parametrize("order,precision,n_bh", [(4, "fp64", 2), (4, "mixed", 2), (6, "fp64", 2), (8, "fp64", 2),
+                                                  (8, "mixed", 2), (4, "fp64", 3), (6, "fp64", 3)])
+def test_pn_init_and_step_parity(order, precision, n_bh):
+    model = _bh_model(n_bh)
+    sim = _sim(model.m, model.x, model.v, precision, 2.0, 5, n_hard=n_bh, order=order,
+               eta=0.01 if order == 4 else 0.1)
     ocfg = _ocfg(sim)
     sim.init()
     h = sim.to_numpy()
@@ -49,13 +66,15 @@ def test_pn_init_and_step_parity(order, precision):
     for k in range(min(order - 2, 4)):
         e = rel_err(h["d"][k], os_.d[k])
         rms = float(np.sqrt(np.mean(e * e)))
-        say("pn init p%d %s d[%d] rms rel %.2e max %.2e (black holes %.2e)"
-            % (order, precision, k, rms, e.max(), e[:2].max()))
-        assert rms <= 1e-12 and e.max() <= 1e-9 and e[:2].max() <= 1e-12
+        say("pn init p%d %s %d BHs d[%d] rms rel %.2e max %.2e (black holes %.2e)"
+            % (order, precision, n_bh, k, rms, e.max(), e[:n_bh].max()))
+        assert rms <= 1e-12 and e.max() <= 1e-9 and e[:n_bh].max() <= 1e-12
     assert np.sum(h["level"] != os_.level) <= 2
     plain = oracle.State(model.m, model.x, model.v, order)
-    oracle.init(OracleConfig(order=order, eps2=ocfg.eps2, n_hard=2, eta=ocfg.eta, eta_start=ocfg.eta_start), plain)
-    shift = np.linalg.norm(os_.d[0][:, :2] - plain.d[0][:, :2], axis=0) / np.linalg.norm(plain.d[0][:, :2], axis=0)
+    oracle.init(OracleConfig(order=order, eps2=ocfg.eps2, n_hard=n_bh, eta=ocfg.eta, eta_start=ocfg.eta_start),
+                plain)
+    shift = (np.linalg.norm(os_.d[0][:, :n_bh] - plain.d[0][:, :n_bh], axis=0)
+             / np.linalg.norm(plain.d[0][:, :n_bh], axis=0))
     say("pn init: relative change of the black holes' acceleration %.2e" % shift.max())
     assert shift.min() > 1e-3                # the terms are on
     rel_force = 1e-11 if precision == "fp64" else 3e-5
@@ -67,7 +86,7 @@ def test_pn_init_and_step_parity(order, precision):
         nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
         T = int(nxt.min())
         act = np.nonzero(nxt == T)[0].astype(np.int32)
-        bh_steps += int(np.sum(act < 2))
+        bh_steps += int(np.sum(act < n_bh))
         t_g, na_g = sim.step()
         assert (t_g, na_g) == (T, act.size), step
         xp, vp, ap, jp = oracle.predict(ocfg, os0, T)

@@ -191,6 +191,35 @@ def test_pairwise_terms_conserve_momentum_and_skip_soft_particles():
     assert np.all(off == 0)
 
 
+def test_three_hard_bodies_conserve_momentum_and_rows_do_not_depend_on_the_active_set():
+    """With three hard bodies each row sums the terms of its two pairs: the
+    total momentum change still vanishes (each pair's share is m2/M and
+    -m1/M of one relative acceleration), and a row computed in a smaller
+    active set has the same bits as in the full one."""
+    rng = np.random.default_rng(33)
+    n = 6
+    m = np.array([0.3, 0.1, 0.2, 1e-3, 1e-3, 1e-3])
+    x = rng.normal(size=(3, n))
+    v = rng.normal(size=(3, n))
+    cfg = OracleConfig(order=8, n_hard=3, c_light=4.0, pn_terms=5)
+    act = np.arange(n, dtype=np.int32)
+    out = [np.zeros((3, n)) for _ in range(4)]
+    oracle.pn(cfg, m, x, v, act, *out)
+    for o in out:
+        scale = np.abs(m[:3] * o[:, :3]).max()
+        assert scale > 0
+        np.testing.assert_allclose(o[:, :3] @ m[:3], 0.0, atol=1e-14 * scale)
+        assert np.all(o[:, 3:] == 0)
+    pair01 = [np.zeros((3, n)) for _ in range(4)]
+    oracle.pn(OracleConfig(order=8, n_hard=2, c_light=4.0, pn_terms=5), m, x, v, act, *pair01)
+    assert np.abs(out[0][:, 0] - pair01[0][:, 0]).max() > 1e-3 * np.abs(pair01[0][:, 0]).max()
+    sub = np.array([1], dtype=np.int32)
+    one = [np.zeros((3, 1)) for _ in range(4)]
+    oracle.pn(cfg, m, x, v, sub, *one)
+    for o, f in zip(one, out):
+        np.testing.assert_array_equal(o[:, 0], f[:, 1])
+
+
 def test_oracle_integration_inspiral_at_peters_rate():
     """The oracle's 4th-order block-step integration of a circular binary
     with the 2.5PN terms alone: the semi-major axis from the Newtonian energy
