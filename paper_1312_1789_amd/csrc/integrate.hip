@@ -112,90 +112,81 @@ k_init_levels(int64_t n, const double *__restrict__ a, const double *__restrict_
 }
 
 // --------------------------------------------------------------------------
-// Scheduler.  Pass 1: per-block minimum of t_i + dt_i.  Pass 2: every block
-// reduces the block minima to t_next and counts its active particles.
-// Pass 3 (one block): exclusive scan of the counts, n_act.  Pass 4: each block
-// writes its active indices in increasing order at its offset.
+// Scheduler.  Pass 1: per block, the minimum of t_i + dt_i and how many of
+// its particles reach it.  Pass 2 (one block): t_next = the least block
+// minimum; exclusive scan of the counts of the blocks whose minimum is t_next
+// (the others have no active particle), n_act.  Pass 3: each block writes its
+// active indices in increasing order at its offset.
 __device__ __forceinline__ int64_t next_time(const int64_t *t_tick, const int32_t *level, int64_t i)
 {
     return t_tick[i] + (int64_t(1) << (kLevelMax - level[i]));
 }
 
+// (minimum, count at the minimum) of two partial results
+__device__ __forceinline__ void min_count(int64_t &m, int &c, int64_t m2, int c2)
+{
+    if (m2 < m) {
+        m = m2;
+        c = c2;
+    } else if (m2 == m) {
+        c += c2;
+    }
+}
+
 __global__ void __launch_bounds__(kSchedBlock)
 k_sched_min(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-            int64_t *__restrict__ bmin)
+            int64_t *__restrict__ bmin, int32_t *__restrict__ bcnt)
 {
     __shared__ int64_t sm[kSchedBlock];
+    __shared__ int sc[kSchedBlock];
     const int64_t base = int64_t(blockIdx.x) * kSchedChunk;
     int64_t mn = INT64_MAX;
-#pragma unroll
-    for (int k = 0; k < kSchedPerThread; ++k) {
-        const int64_t i = base + int64_t(k) * kSchedBlock + threadIdx.x;
-        if (i < n) {
-            const int64_t tn = next_time(t_tick, level, i);
-            mn = tn < mn ? tn : mn;
-        }
-    }
-    sm[threadIdx.x] = mn;
-    __syncthreads();
-    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) sm[threadIdx.x] = sm[threadIdx.x + s] < sm[threadIdx.x] ? sm[threadIdx.x + s] : sm[threadIdx.x];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) bmin[blockIdx.x] = sm[0];
-}
-
-__device__ __forceinline__ int64_t block_min_all(const int64_t *bmin, int nb, int64_t *sm)
-{
-    int64_t mn = INT64_MAX;
-    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
-    sm[threadIdx.x] = mn;
-    __syncthreads();
-    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) sm[threadIdx.x] = sm[threadIdx.x + s] < sm[threadIdx.x] ? sm[threadIdx.x + s] : sm[threadIdx.x];
-        __syncthreads();
-    }
-    const int64_t r = sm[0];
-    __syncthreads();
-    return r;
-}
-
-__global__ void __launch_bounds__(kSchedBlock)
-k_sched_count(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-              const int64_t *__restrict__ bmin, int nb, int32_t *__restrict__ bcnt, DevScalars *__restrict__ sc)
-{
-    __shared__ int64_t sm[kSchedBlock];
-    __shared__ int cnt[kSchedBlock];
-    const int64_t tn = block_min_all(bmin, nb, sm);
-    const int64_t base = int64_t(blockIdx.x) * kSchedChunk;
     int c = 0;
 #pragma unroll
     for (int k = 0; k < kSchedPerThread; ++k) {
         const int64_t i = base + int64_t(k) * kSchedBlock + threadIdx.x;
-        if (i < n && next_time(t_tick, level, i) == tn) ++c;
+        if (i < n) min_count(mn, c, next_time(t_tick, level, i), 1);
     }
-    cnt[threadIdx.x] = c;
+    sm[threadIdx.x] = mn;
+    sc[threadIdx.x] = c;
     __syncthreads();
     for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
+        if (int(threadIdx.x) < s) {
+            int64_t m = sm[threadIdx.x];
+            int cc = sc[threadIdx.x];
+            min_count(m, cc, sm[threadIdx.x + s], sc[threadIdx.x + s]);
+            sm[threadIdx.x] = m;
+            sc[threadIdx.x] = cc;
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        bcnt[blockIdx.x] = cnt[0];
-        if (blockIdx.x == 0) sc->t_next = tn;
+        bmin[blockIdx.x] = sm[0];
+        bcnt[blockIdx.x] = sc[0];
     }
 }
 
 __global__ void __launch_bounds__(kSchedBlock)
-k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ boff, DevScalars *__restrict__ sc,
-             HostScalars *__restrict__ pub, int64_t seq)
+k_sched_scan(const int64_t *__restrict__ bmin, const int32_t *__restrict__ bcnt, int nb,
+             int64_t *__restrict__ boff, DevScalars *__restrict__ sc, HostScalars *__restrict__ pub, int64_t seq)
 {
-    // one block: sequential chunks of kSchedBlock, scanned in LDS
+    // one block: t_next from the block minima, then sequential chunks of
+    // kSchedBlock counts scanned in LDS
     __shared__ int64_t s[kSchedBlock];
+    int64_t mn = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
+    s[threadIdx.x] = mn;
+    __syncthreads();
+    for (int o = kSchedBlock / 2; o > 0; o >>= 1) {
+        if (int(threadIdx.x) < o) s[threadIdx.x] = s[threadIdx.x + o] < s[threadIdx.x] ? s[threadIdx.x + o] : s[threadIdx.x];
+        __syncthreads();
+    }
+    const int64_t tn = s[0];
+    __syncthreads();
     int64_t carry = 0;
     for (int b0 = 0; b0 < nb; b0 += kSchedBlock) {
         const int b = b0 + threadIdx.x;
-        const int64_t v = b < nb ? bcnt[b] : 0;
+        const int64_t v = (b < nb && bmin[b] == tn) ? bcnt[b] : 0;
         s[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < kSchedBlock; o <<= 1) {
@@ -209,11 +200,12 @@ k_sched_scan(const int32_t *__restrict__ bcnt, int nb, int64_t *__restrict__ bof
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        sc->t_next = tn;
         sc->n_act = carry;
         if (pub) {
             // the fields first, then (after a system-scope fence) the
             // sequence number the host waits for
-            pub->t_next = sc->t_next;
+            pub->t_next = tn;
             pub->n_act = carry;
             pub->underflow = sc->underflow;
             pub->nonfinite = sc->nonfinite;
@@ -383,9 +375,8 @@ hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *leve
     int64_t *bmin = static_cast<int64_t *>(scratch);
     int64_t *boff = bmin + nb;
     int32_t *bcnt = reinterpret_cast<int32_t *>(boff + nb);
-    hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin);
-    hipLaunchKernelGGL(k_sched_count, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, nb, bcnt, sc);
-    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bcnt, nb, boff, sc, pub, seq);
+    hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, bcnt);
+    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bmin, bcnt, nb, boff, sc, pub, seq);
     hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, boff, sc, act_out);
     return hipGetLastError();
 }

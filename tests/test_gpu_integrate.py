@@ -52,6 +52,40 @@ def test_schedule_exact():
         np.testing.assert_array_equal(act.cpu().numpy(), want)
 
 
+def test_schedule_block_minima():
+    """Crafted states for the per-block (minimum, count at the minimum) pass,
+    n = 5003 (five scheduling blocks of 1024, a ragged last one): every
+    particle active; one active particle in the ragged block while every
+    other block has many particles tied at a larger minimum of its own; the
+    global minimum reached in two blocks only, with ties inside a block."""
+    n = 5003
+    model = nbody_ics.plummer(n, 5)
+    sim = _sim(model, 4)
+    cases = []
+    cases.append((np.zeros(n, np.int64), np.full(n, 5, np.int32)))
+    t = np.zeros(n, np.int64)
+    lv = np.full(n, 6, np.int32)
+    lv[::7] = 8                      # block minima at 2^12 ticks, many ties per block
+    lv[5002] = 9                     # the global minimum, 2^11, in the ragged block
+    cases.append((t, lv))
+    t = np.full(n, 1 << 14, np.int64)
+    lv = np.full(n, 4, np.int32)
+    lv[100:140] = 7                  # block 0: 40 ties at a larger minimum
+    lv[[1500, 3100, 3101]] = 9       # the global minimum in blocks 1 and 3
+    lv[4200:4300] = 8                # block 4: ties at an intermediate value
+    cases.append((t, lv))
+    for k, (t, lv) in enumerate(cases):
+        sim.load_state(model.x, model.v, [np.zeros((3, n))] * 2, t, lv)
+        t_next, act = sim.schedule()
+        nxt = t + (1 << (20 - lv.astype(np.int64)))
+        want_t = int(nxt.min())
+        want = np.nonzero(nxt == want_t)[0]
+        say("schedule case %d: t_next %d, n_act %d" % (k, want_t, want.size))
+        assert t_next == want_t
+        np.testing.assert_array_equal(act.cpu().numpy(), want)
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "ds"])
 @pytest.mark.parametrize("order", [4, 6, 8])
 def test_predict_parity(order, precision):
