@@ -112,11 +112,16 @@ k_init_levels(int64_t n, const double *__restrict__ a, const double *__restrict_
 }
 
 // --------------------------------------------------------------------------
-// Scheduler.  Pass 1: per block, the minimum of t_i + dt_i and how many of
-// its particles reach it.  Pass 2 (one block): t_next = the least block
-// minimum; exclusive scan of the counts of the blocks whose minimum is t_next
-// (the others have no active particle), n_act.  Pass 3: each block writes its
-// active indices in increasing order at its offset.
+// Scheduler.  Pass 1: per block of kSchedChunk particles, the minimum of
+// t_i + dt_i and how many of its particles reach it.  With at most
+// kSchedOwnOffsets blocks, pass 2 is the compaction itself: every block takes
+// t_next as the least block minimum and its output offset as the number of
+// particles at t_next in the blocks before it (block 0 also publishes t_next
+// and n_act), then writes its active indices in increasing order.  With more
+// blocks a one-block kernel computes t_next and the offsets first.
+constexpr int kSchedWaves = kSchedBlock / 64;
+constexpr int kSchedOwnOffsets = 1024;   // blocks (n <= 2^20) for which each block finds its own offset
+
 __device__ __forceinline__ int64_t next_time(const int64_t *t_tick, const int32_t *level, int64_t i)
 {
     return t_tick[i] + (int64_t(1) << (kLevelMax - level[i]));
@@ -133,12 +138,61 @@ __device__ __forceinline__ void min_count(int64_t &m, int &c, int64_t m2, int c2
     }
 }
 
+__device__ __forceinline__ int64_t wave_min(int64_t m)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t t = __shfl_xor(m, o, 64);
+        m = t < m ? t : m;
+    }
+    return m;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive prefix of c over the block's threads in thread order (wave
+// scans, then the wave totals through LDS).  Synchronises the block.
+__device__ __forceinline__ int block_excl_scan(int c, int *wsum)
+{
+    const int lane = int(threadIdx.x) & 63, w = int(threadIdx.x) >> 6;
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    return before + incl - c;
+}
+
+// The step's t_next and n_act into the device scalars and, when given, the
+// pinned host copy: the fields first, then (after a system-scope fence) the
+// sequence number the host waits for.
+__device__ __forceinline__ void publish(DevScalars *sc, HostScalars *pub, int64_t seq, int64_t tn, int64_t n_act)
+{
+    sc->t_next = tn;
+    sc->n_act = n_act;
+    if (pub) {
+        pub->t_next = tn;
+        pub->n_act = n_act;
+        pub->underflow = sc->underflow;
+        pub->nonfinite = sc->nonfinite;
+        __threadfence_system();
+        __hip_atomic_store(&pub->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 __global__ void __launch_bounds__(kSchedBlock)
 k_sched_min(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
             int64_t *__restrict__ bmin, int32_t *__restrict__ bcnt)
 {
-    __shared__ int64_t sm[kSchedBlock];
-    __shared__ int sc[kSchedBlock];
+    __shared__ int64_t wm[kSchedWaves];
+    __shared__ int wc[kSchedWaves];
     const int64_t base = int64_t(blockIdx.x) * kSchedChunk;
     int64_t mn = INT64_MAX;
     int c = 0;
@@ -147,80 +201,29 @@ k_sched_min(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__rest
         const int64_t i = base + int64_t(k) * kSchedBlock + threadIdx.x;
         if (i < n) min_count(mn, c, next_time(t_tick, level, i), 1);
     }
-    sm[threadIdx.x] = mn;
-    sc[threadIdx.x] = c;
-    __syncthreads();
-    for (int s = kSchedBlock / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) {
-            int64_t m = sm[threadIdx.x];
-            int cc = sc[threadIdx.x];
-            min_count(m, cc, sm[threadIdx.x + s], sc[threadIdx.x + s]);
-            sm[threadIdx.x] = m;
-            sc[threadIdx.x] = cc;
-        }
-        __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t m2 = __shfl_xor(mn, o, 64);
+        const int c2 = __shfl_xor(c, o, 64);
+        min_count(mn, c, m2, c2);
     }
+    if ((threadIdx.x & 63) == 0) {
+        wm[threadIdx.x >> 6] = mn;
+        wc[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        bmin[blockIdx.x] = sm[0];
-        bcnt[blockIdx.x] = sc[0];
+        for (int k = 1; k < kSchedWaves; ++k) min_count(mn, c, wm[k], wc[k]);
+        bmin[blockIdx.x] = mn;
+        bcnt[blockIdx.x] = c;
     }
 }
 
-__global__ void __launch_bounds__(kSchedBlock)
-k_sched_scan(const int64_t *__restrict__ bmin, const int32_t *__restrict__ bcnt, int nb,
-             int64_t *__restrict__ boff, DevScalars *__restrict__ sc, HostScalars *__restrict__ pub, int64_t seq)
+// This block's particles at t_next written from act[off] on, in increasing
+// index order (each thread takes kSchedPerThread consecutive particles).
+__device__ __forceinline__ void compact_block(int64_t n, const int64_t *__restrict__ t_tick,
+                                              const int32_t *__restrict__ level, int64_t tn, int64_t off,
+                                              int *wsum, int32_t *__restrict__ act)
 {
-    // one block: t_next from the block minima, then sequential chunks of
-    // kSchedBlock counts scanned in LDS
-    __shared__ int64_t s[kSchedBlock];
-    int64_t mn = INT64_MAX;
-    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
-    s[threadIdx.x] = mn;
-    __syncthreads();
-    for (int o = kSchedBlock / 2; o > 0; o >>= 1) {
-        if (int(threadIdx.x) < o) s[threadIdx.x] = s[threadIdx.x + o] < s[threadIdx.x] ? s[threadIdx.x + o] : s[threadIdx.x];
-        __syncthreads();
-    }
-    const int64_t tn = s[0];
-    __syncthreads();
-    int64_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += kSchedBlock) {
-        const int b = b0 + threadIdx.x;
-        const int64_t v = (b < nb && bmin[b] == tn) ? bcnt[b] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < kSchedBlock; o <<= 1) {
-            const int64_t add = int(threadIdx.x) >= o ? s[threadIdx.x - o] : 0;
-            __syncthreads();
-            s[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (b < nb) boff[b] = carry + s[threadIdx.x] - v;
-        carry += s[kSchedBlock - 1];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        sc->t_next = tn;
-        sc->n_act = carry;
-        if (pub) {
-            // the fields first, then (after a system-scope fence) the
-            // sequence number the host waits for
-            pub->t_next = tn;
-            pub->n_act = carry;
-            pub->underflow = sc->underflow;
-            pub->nonfinite = sc->nonfinite;
-            __threadfence_system();
-            __hip_atomic_store(&pub->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kSchedBlock)
-k_sched_compact(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-                const int64_t *__restrict__ boff, const DevScalars *__restrict__ sc, int32_t *__restrict__ act)
-{
-    __shared__ int s[kSchedBlock];
-    const int64_t tn = sc->t_next;
     const int64_t base = int64_t(blockIdx.x) * kSchedChunk + int64_t(threadIdx.x) * kSchedPerThread;
     int flags[kSchedPerThread];
     int c = 0;
@@ -230,18 +233,88 @@ k_sched_compact(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__
         flags[k] = (i < n && next_time(t_tick, level, i) == tn) ? 1 : 0;
         c += flags[k];
     }
-    s[threadIdx.x] = c;
-    __syncthreads();
-    for (int o = 1; o < kSchedBlock; o <<= 1) {
-        const int add = int(threadIdx.x) >= o ? s[threadIdx.x - o] : 0;
-        __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    int64_t pos = boff[blockIdx.x] + s[threadIdx.x] - c;
+    int64_t pos = off + block_excl_scan(c, wsum);
 #pragma unroll
     for (int k = 0; k < kSchedPerThread; ++k)
-        if (flags[k]) act[pos++] = int32_t(base + k);
+        if (flags[k] && pos < n) act[pos++] = int32_t(base + k);
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_compact_own(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+                    const int64_t *__restrict__ bmin, const int32_t *__restrict__ bcnt, int nb,
+                    DevScalars *__restrict__ sc, HostScalars *__restrict__ pub, int64_t seq,
+                    int32_t *__restrict__ act)
+{
+    __shared__ int64_t wm[kSchedWaves], wo[kSchedWaves], wt[kSchedWaves];
+    __shared__ int wsum[kSchedWaves];
+    const int lane = int(threadIdx.x) & 63, w = int(threadIdx.x) >> 6;
+    int64_t mn = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
+    mn = wave_min(mn);
+    if (lane == 0) wm[w] = mn;
+    __syncthreads();
+    int64_t tn = wm[0];
+    for (int k = 1; k < kSchedWaves; ++k) tn = wm[k] < tn ? wm[k] : tn;
+    // particles at t_next in the blocks before this one, and in all blocks
+    int64_t off = 0, tot = 0;
+    for (int b = threadIdx.x; b < nb; b += kSchedBlock) {
+        const int64_t v = bmin[b] == tn ? bcnt[b] : 0;
+        tot += v;
+        if (b < int(blockIdx.x)) off += v;
+    }
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    if (lane == 0) {
+        wo[w] = off;
+        wt[w] = tot;
+    }
+    __syncthreads();
+    off = 0;
+    tot = 0;
+    for (int k = 0; k < kSchedWaves; ++k) {
+        off += wo[k];
+        tot += wt[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish(sc, pub, seq, tn, tot);
+    compact_block(n, t_tick, level, tn, off, wsum, act);
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_scan(const int64_t *__restrict__ bmin, const int32_t *__restrict__ bcnt, int nb,
+             int64_t *__restrict__ boff, DevScalars *__restrict__ sc, HostScalars *__restrict__ pub, int64_t seq)
+{
+    // one block: t_next from the block minima, then sequential chunks of
+    // kSchedBlock counts scanned with wave scans
+    __shared__ int64_t wm[kSchedWaves];
+    __shared__ int wsum[kSchedWaves];
+    const int lane = int(threadIdx.x) & 63, w = int(threadIdx.x) >> 6;
+    int64_t mn = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kSchedBlock) mn = bmin[b] < mn ? bmin[b] : mn;
+    mn = wave_min(mn);
+    if (lane == 0) wm[w] = mn;
+    __syncthreads();
+    int64_t tn = wm[0];
+    for (int k = 1; k < kSchedWaves; ++k) tn = wm[k] < tn ? wm[k] : tn;
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kSchedBlock) {
+        const int b = b0 + threadIdx.x;
+        const int v = (b < nb && bmin[b] == tn) ? bcnt[b] : 0;   // <= kSchedChunk
+        const int ex = block_excl_scan(v, wsum);
+        if (b < nb) boff[b] = carry + ex;
+        int chunk = 0;
+        for (int k = 0; k < kSchedWaves; ++k) chunk += wsum[k];
+        carry += chunk;
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (threadIdx.x == 0) publish(sc, pub, seq, tn, carry);
+}
+
+__global__ void __launch_bounds__(kSchedBlock)
+k_sched_compact(int64_t n, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
+                const int64_t *__restrict__ boff, const DevScalars *__restrict__ sc, int32_t *__restrict__ act)
+{
+    __shared__ int wsum[kSchedWaves];
+    compact_block(n, t_tick, level, sc->t_next, boff[blockIdx.x], wsum, act);
 }
 
 // --------------------------------------------------------------------------
@@ -376,8 +449,14 @@ hipError_t launch_schedule(int64_t n, const int64_t *t_tick, const int32_t *leve
     int64_t *boff = bmin + nb;
     int32_t *bcnt = reinterpret_cast<int32_t *>(boff + nb);
     hipLaunchKernelGGL(k_sched_min, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, bcnt);
-    hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bmin, bcnt, nb, boff, sc, pub, seq);
-    hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, boff, sc, act_out);
+    if (nb <= kSchedOwnOffsets) {
+        hipLaunchKernelGGL(k_sched_compact_own, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, bmin, bcnt, nb,
+                           sc, pub, seq, act_out);
+    } else {
+        hipLaunchKernelGGL(k_sched_scan, dim3(1), dim3(kSchedBlock), 0, s, bmin, bcnt, nb, boff, sc, pub, seq);
+        hipLaunchKernelGGL(k_sched_compact, dim3(nb), dim3(kSchedBlock), 0, s, n, t_tick, level, boff, sc,
+                           act_out);
+    }
     return hipGetLastError();
 }
 

@@ -38,7 +38,10 @@ def _ostate(h, order):
 
 
 def test_schedule_exact():
-    for n, seed in [(1, 1), (1000, 2), (5003, 3), (70000, 4)]:
+    # n = 2^20 is the largest system whose compaction blocks find their own
+    # offsets (1024 scheduling blocks); 2^20 + 3000 takes the path with a
+    # separate one-block scan
+    for n, seed in [(1, 1), (1000, 2), (5003, 3), (70000, 4), (1 << 20, 6), ((1 << 20) + 3000, 7)]:
         model = nbody_ics.plummer(max(n, 2), seed)
         sim = _sim(model, 4)
         t, lv = random_block_state(model.n, seed)
