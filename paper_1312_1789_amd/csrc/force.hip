@@ -26,6 +26,14 @@ namespace {
 // n_hard the self pair is evaluated with eps2 > 0 (its acceleration and
 // derivatives are exactly zero, every difference being zero), except in the
 // kernels that also sum the potential, which mask it by index.
+//
+// Partial sums of launches with more than kSplitFastestAbove splits are
+// stored split-fastest, part[component][row][split], so that the lanes
+// reducing one output read consecutive splits; with fewer splits (one lane
+// or four per output) row-fastest, part[split][component][row], so that a
+// workgroup's stores are coalesced.
+constexpr int kSplitFastestAbove = 32;
+
 template <class Pol, int P, int NI>
 __device__ __forceinline__ void store_rows(int64_t n_act, int64_t row0, int split, int n_split,
                                            double (*acc)[13], double *__restrict__ o_acc,
@@ -47,6 +55,12 @@ __device__ __forceinline__ void store_rows(int64_t n_act, int64_t row0, int spli
                 if (o) o[(c % 3) * n_act + q] = acc[k][c];
             }
             if (Pol::kWithPot && o_pot) o_pot[q] = -pot;
+        } else if (n_split > kSplitFastestAbove) {
+            double *base = part + q * n_split + split;
+            const int64_t cs = n_act * n_split;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) base[c * cs] = acc[k][c];
+            if (Pol::kWithPot) base[NV * cs] = -pot;
         } else {
             constexpr int NC = NV + 1;
             double *base = part + int64_t(split) * NC * n_act;
@@ -213,11 +227,13 @@ k_force_ws(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *
         }
         if (Pol::kWithPot && o_pot) o_pot[q] = -acc[kPot];
     } else {
-        constexpr int NC = NV + 1;
-        double *base = part + int64_t(split) * NC * n_act;
+        // split-fastest partial sums: the reduction's lanes then read
+        // consecutive splits of one output
+        double *base = part + q * n_split + split;
+        const int64_t cs = n_act * n_split;
 #pragma unroll
-        for (int c = 0; c < NV; ++c) base[int64_t(c) * n_act + q] = acc[c];
-        if (Pol::kWithPot) base[int64_t(NV) * n_act + q] = -acc[kPot];
+        for (int c = 0; c < NV; ++c) base[c * cs] = acc[c];
+        if (Pol::kWithPot) base[NV * cs] = -acc[kPot];
     }
 }
 
@@ -225,8 +241,12 @@ k_force_ws(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *
 // 64, consecutive lanes of one wavefront) owns one output value: lane l adds
 // splits l, l + L, l + 2L, ... in order, then the group folds its L sums with
 // a fixed butterfly of cross-lane exchanges.  The order depends only on
-// n_split and L, so reruns are bitwise identical.
-template <int P, int L>
+// n_split and L, so reruns are bitwise identical.  Layouts: SF = false,
+// part[split][component][row] (kernels A and B with at most
+// kSplitFastestAbove splits: a workgroup's lanes write consecutive rows);
+// SF = true, part[component][row][split] (kernels A and B with more splits,
+// and the wave j-split kernels: a group's lanes read consecutive splits).
+template <int P, int L, bool SF>
 __global__ void __launch_bounds__(256)
 k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__restrict__ o_acc,
          double *__restrict__ o_jrk, double *__restrict__ o_snp, double *__restrict__ o_crk,
@@ -244,8 +264,8 @@ k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__
     if (valid) {
         // the loads of eight splits are issued together (one memory round
         // trip instead of eight); the values are still added in split order
-        const double *src = part + int64_t(c) * n_act + q;
-        const int64_t step = int64_t(NC) * n_act;
+        const double *src = SF ? part + (int64_t(c) * n_act + q) * n_split : part + int64_t(c) * n_act + q;
+        const int64_t step = SF ? 1 : int64_t(NC) * n_act;
         int sp = l;
         for (; sp + 7 * L < n_split; sp += 8 * L) {
             double v[8];
@@ -268,14 +288,14 @@ k_reduce(const double *__restrict__ part, int64_t n_act, int n_split, double *__
     if (o) o[(c % 3) * n_act + q] = s;
 }
 
-template <int P>
+template <int P, bool SF>
 hipError_t launch_reduce(const ForceArgs &a, int n_split, hipStream_t s)
 {
     const int64_t outs = a.n_act * (3 * (P / 2) + 1);
     // lanes per output: enough that each lane adds at most about 8 splits
     const int L = n_split <= 8 ? 1 : n_split <= 32 ? 4 : n_split <= 128 ? 16 : 64;
     const unsigned blocks = unsigned((outs * L + 255) / 256);
-#define NB_RED(LL) hipLaunchKernelGGL((k_reduce<P, LL>), dim3(blocks), dim3(256), 0, s, a.part, a.n_act, n_split, \
+#define NB_RED(LL) hipLaunchKernelGGL((k_reduce<P, LL, SF>), dim3(blocks), dim3(256), 0, s, a.part, a.n_act, n_split, \
                                       a.out[0], a.out[1], a.out[2], a.out[3], a.out[4])
     if (L == 1) NB_RED(1);
     else if (L == 4) NB_RED(4);
@@ -318,7 +338,8 @@ hipError_t run(const ForceArgs &a, hipStream_t s, const Shape &sh)
 #undef NB_FORCE_ARGS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || sh.n_split == 1) return e;
-    return launch_reduce<P>(a, sh.n_split, s);
+    if (sh.jpath == 3 || sh.n_split > kSplitFastestAbove) return launch_reduce<P, true>(a, sh.n_split, s);
+    return launch_reduce<P, false>(a, sh.n_split, s);
 }
 
 template <class Pol, int P>
@@ -404,11 +425,11 @@ void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, i
     *n_split = int((n + jc - 1) / jc);
 }
 
-hipError_t launch_split_reduce(int order, const ForceArgs &a, int n_split, hipStream_t s)
+hipError_t launch_split_reduce_sf(int order, const ForceArgs &a, int n_split, hipStream_t s)
 {
-    if (order == 4) return launch_reduce<4>(a, n_split, s);
-    if (order == 6) return launch_reduce<6>(a, n_split, s);
-    return launch_reduce<8>(a, n_split, s);
+    if (order == 4) return launch_reduce<4, true>(a, n_split, s);
+    if (order == 6) return launch_reduce<6, true>(a, n_split, s);
+    return launch_reduce<8, true>(a, n_split, s);
 }
 
 hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split)

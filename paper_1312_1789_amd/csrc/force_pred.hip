@@ -147,11 +147,12 @@ k_force_wsp(PredIn in, int64_t n, const int32_t *__restrict__ act, int64_t n_act
         }
         if (Pol::kWithPot && o_pot) o_pot[q] = -acc[kPot];
     } else {
-        constexpr int NC = NV + 1;
-        double *base = part + int64_t(split) * NC * n_act;
+        // split-fastest partial sums, as the unfused wave j-split kernel
+        double *base = part + q * n_split + split;
+        const int64_t cs = n_act * n_split;
 #pragma unroll
-        for (int c = 0; c < NV; ++c) base[int64_t(c) * n_act + q] = acc[c];
-        if (Pol::kWithPot) base[int64_t(NV) * n_act + q] = -acc[kPot];
+        for (int c = 0; c < NV; ++c) base[c * cs] = acc[c];
+        if (Pol::kWithPot) base[NV * cs] = -acc[kPot];
     }
 }
 
@@ -170,7 +171,7 @@ hipError_t run(const ForceArgs &a, const PredIn &in, hipStream_t s, int n_split,
 #undef NB_WSP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_split == 1) return e;
-    return launch_split_reduce(P, a, n_split, s);
+    return launch_split_reduce_sf(P, a, n_split, s);
 }
 
 template <int P, bool POT>

@@ -100,7 +100,8 @@ void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, i
                  int64_t *j_chunk);
 
 // Fixed-order sum of n_split partial results in a.part into a.out.
-hipError_t launch_split_reduce(int order, const ForceArgs &a, int n_split, hipStream_t s);
+// the split reduction for partial sums in part[component][row][split] (wave j-split kernels)
+hipError_t launch_split_reduce_sf(int order, const ForceArgs &a, int n_split, hipStream_t s);
 
 // The stored state the predictor reads, and the time it predicts to.
 struct PredIn {

@@ -114,6 +114,37 @@ def test_launch_shapes_and_determinism(small_case, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_layouts(precision):
+    """Partial sums of launches with more than 32 j-splits are stored
+    split-fastest, with fewer row-fastest.  n = 20000 (King W0=7 + black-hole
+    binary), order 6, 300 active rows: for requests of 16, 64 and 160 splits
+    (16, 53 and 157 after rounding to whole 128-particle chunks: row-fastest,
+    then split-fastest with 16 and 64 reduction lanes per output) every
+    i-tile shape and j path gives the same bits, and the result matches the
+    oracle."""
+    model = cluster_with_bh(19998, 23)
+    eps2, n_hard = 1e-8, 2
+    a, j = physical_derivs(model.m, model.x, model.v, eps2, n_hard)
+    d = [a, j, np.zeros_like(a), np.zeros_like(a), np.zeros_like(a), np.zeros_like(a)]
+    sim = _sim(model, 6, precision, eps2, n_hard, d)
+    act_np = nbody_ics.active_subset(model.n, 300, 1560)
+    act = torch.as_tensor(act_np, device=sim.device)
+    ref = oracle_force(6, eps2, n_hard, model.m, model.x, model.v, d[0], d[1], act=act_np)
+    for n_split in (16, 64, 160):
+        first = None
+        for ni, block, jpath in [(1, 256, 1), (2, 128, 1), (1, 64, 2), (2, 256, 2)]:
+            sim.set_launch(ni, block, n_split, jpath)
+            out = {k: t.cpu().numpy().copy() for k, t in sim.force_block(act).items()}
+            if first is None:
+                first = out
+                say("split layouts %s: %d splits" % (precision, n_split))
+                _check(sim.force_block(act), ref, 6, precision, act_np.size)
+            for k in ("acc", "jrk", "snp", "pot"):
+                np.testing.assert_array_equal(out[k], first[k])
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_autotuned_launch_keeps_parity(small_case, precision):
     """nbody_autotune fills one row per power-of-two active size with a valid
     shape; force calls then take their shape from the table and still match
