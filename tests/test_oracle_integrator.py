@@ -163,8 +163,68 @@ def test_dt_crit_order4_form(oracle_lib, p):
     H = F.copy()
     H[3] *= 4.0
     assert oracle.dt_crit(p, eta, H, rule=2) < oracle.dt_crit(p, eta, F, rule=2)
-    # the full-order criterion does read the higher derivatives
-    assert oracle.dt_crit(p, eta, G * np.r_[1, 1, 1, 1, [2.0] * (p - 4)], rule=1) != oracle.dt_crit(p, eta, F, rule=1)
+    # the full-order criterion does read the higher derivatives (finite
+    # values: a NaN would make any comparison pass)
+    K = F * np.r_[1, 1, 1, 1, [2.0] * (p - 4)]
+    assert np.isfinite(oracle.dt_crit(p, eta, K, rule=1))
+    assert oracle.dt_crit(p, eta, K, rule=1) != oracle.dt_crit(p, eta, F, rule=1)
+
+
+@pytest.mark.parametrize("p,F", [
+    # p = 6: A_1 = sqrt(1*1) + 1 = 2, A_4 = sqrt(|a^(3)||a^(5)|) + |a^(4)| = sqrt(4*9) + 10 = 16,
+    #        dt = eta (2/16)^(1/3) = eta/2
+    (6, [1.0, 1.0, 1.0, 4.0, 10.0, 9.0]),
+    # p = 8: A_1 = 2, A_6 = sqrt(|a^(5)||a^(7)|) + |a^(6)| = sqrt(4*100) + 44 = 64,
+    #        dt = eta (2/64)^(1/5) = eta/2
+    (8, [1.0, 1.0, 1.0, 3.0, 7.0, 4.0, 44.0, 100.0]),
+])
+def test_dt_crit_full_order_hand_values(oracle_lib, p, F):
+    """The generalised criterion of the scheme's order, dt = eta (A_1/A_(p-2))^(1/(p-3))
+    with A_k = sqrt(|a^(k-1)||a^(k+1)|) + |a^(k)| (Nitadori & Makino 2008), on
+    derivative magnitudes that are not a geometric sequence, so that an index
+    or exponent slip changes the value.  At p = 6, A_(p-3) in place of
+    A_(p-2) gives eta * 0.654, the exponent 1/(p-4) eta * 0.354, both slips
+    eta * 0.528; at p = 8 eta * 0.622, 0.420 and 0.552.  Both cases are built
+    to give exactly eta/2 (arithmetic in the parameter list)."""
+    eta = 0.1
+    got = oracle.dt_crit(p, eta, np.array(F), rule=1)
+    assert abs(got - eta / 2) < 1e-15, got
+    # the order-4 form on the same input: eta A_1/A_2, A_2 = sqrt(|a^(1)||a^(3)|) + |a^(2)|
+    A2 = math.sqrt(F[1] * F[3]) + F[2]
+    assert abs(oracle.dt_crit(p, eta, np.array(F), rule=2) - eta * 2.0 / A2) < 1e-15
+
+
+@pytest.mark.parametrize("eta_start,level", [(0.01, 10), (0.02, 9), (0.003, 12)])
+def test_init_first_level_circular_binary(oracle_lib, eta_start, level):
+    """The initial step dt0 = eta_start |a|/|jerk|, quantised to the largest
+    2^-k <= dt0.  Two equal unsoftened masses 1/2 on a circular orbit of
+    separation r = 1/4 have angular frequency w = sqrt(M/r^3) = 8, and for each
+    body |jerk| = w |a|, so dt0 = eta_start/8 in closed form:
+    0.01/8 = 1.25e-3 lies in [2^-10, 2^-9), 0.02/8 in [2^-9, 2^-8),
+    0.003/8 = 3.75e-4 in [2^-12, 2^-11).  The inverted ratio |jerk|/|a| would
+    give levels 4, 3 and 6."""
+    r, M = 0.25, 1.0
+    vrel = math.sqrt(M / r)
+    x = np.array([[-r / 2, r / 2], [0.0, 0.0], [0.0, 0.0]])
+    v = np.array([[0.0, 0.0], [-vrel / 2, vrel / 2], [0.0, 0.0]])
+    for p in ORDERS:
+        cfg = OracleConfig(order=p, eps2=0.0, eta=0.1, eta_start=eta_start, k_min=3, k_max=20)
+        s = oracle.State(np.array([0.5, 0.5]), x, v, p)
+        oracle.init(cfg, s)
+        a, j = s.d[0], s.d[1]
+        np.testing.assert_allclose(np.linalg.norm(a, axis=0), 0.5 * M / r ** 2 * 1.0, rtol=1e-14)
+        np.testing.assert_allclose(np.linalg.norm(j, axis=0), 8.0 * np.linalg.norm(a, axis=0), rtol=1e-14)
+        assert list(s.level) == [level, level], (p, s.level)
+        assert list(s.t_tick) == [0, 0]
+    # the clamp to [k_min, k_max] applies to the first step too
+    cfg = OracleConfig(order=4, eps2=0.0, eta=0.01, eta_start=eta_start, k_min=3, k_max=level - 2)
+    s = oracle.State(np.array([0.5, 0.5]), x, v, 4)
+    oracle.init(cfg, s)
+    assert list(s.level) == [level - 2, level - 2]
+    cfg = OracleConfig(order=4, eps2=0.0, eta=0.01, eta_start=eta_start, k_min=level + 3, k_max=20)
+    s = oracle.State(np.array([0.5, 0.5]), x, v, 4)
+    oracle.init(cfg, s)
+    assert list(s.level) == [level + 3, level + 3]
 
 
 def test_dt_crit_aarseth_mixed_magnitudes(oracle_lib):
