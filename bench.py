@@ -45,9 +45,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s & % VALU peak, 6th-order N=1M, mixed vs FP64 at stated error"
-# Algorithmic flops per pair interaction (minimal operation list of the
-# pairwise force with potential; add/sub/mul = 1, FMA = 2, rsqrt = 1):
-FLOPS_PER_INTERACTION = {4: 43, 6: 80, 8: 127}
+# Algorithmic flops per pair interaction: the minimal operation list of the
+# pairwise force with its potential (add/sub/mul = 1, FMA = 2, rsqrt = 1) is
+# 43 / 80 / 127 at orders 4 / 6 / 8, 2 of them the potential's.  The force
+# kernels of a block step, and every kernel timed here, do not sum the
+# potential, so their work is 41 / 78 / 125 flops per interaction.
+FLOPS_WITH_POT = {4: 43, 6: 80, 8: 127}
+FLOPS_PER_INTERACTION = {4: 41, 6: 78, 8: 125}
 # The count commonly quoted for Hermite N-body codes (weights rsqrt heavier):
 FLOPS_LITERATURE = {4: 60, 6: 97, 8: 144}
 # VALU peaks of MI355X: 256 CUs x 4 SIMDs x 64 lanes x 2 flops (FMA) x 2.4 GHz
@@ -94,8 +98,7 @@ def read_traffic(n_act: int, n: int, shape):
         return None
     if int(vals.get("n", -1)) != n or int(vals.get("n_act", -1)) != n_act:
         return None
-    if shape is None or vals.get("launch") != "%d,%d,%d,%d" % (shape["ni"], shape["block"], shape["n_split"],
-                                                               shape["jpath"]):
+    if shape is None or vals.get("launch") != "%d,%d,%d,%d" % tuple(shape):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -103,13 +106,25 @@ def read_traffic(n_act: int, n: int, shape):
         return None
 
 
-def kernel_name(shape, order):
-    """The force kernel a MIXED launch shape runs (scalar or LDS j path)."""
-    if shape is None:
-        return "k_force_lds<PolMx<%d>> (MIXED pairwise force, default shape)" % order
-    k = "k_force" if shape["jpath"] == 1 else "k_force_lds"
-    return "%s<PolMx<%d>, ni=%d> block %d, %d j-splits (MIXED pairwise force)" % (
-        k, order, shape["ni"], shape["block"], shape["n_split"])
+def kernel_name(used, order):
+    """The force kernel a MIXED launch ran, from the shape the library
+    reports for it (ni, block, n_split, jpath)."""
+    ni, block, n_split, jpath = used
+    k = {1: "k_force", 2: "k_force_lds", 3: "k_force_ws"}.get(jpath, "k_force")
+    return "%s<PolMx<%d, no potential>, ni=%d> block %d, %d j-splits (MIXED pairwise force)" % (
+        k, order, ni, block, n_split)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def run_precision(model, precision, order, steps, warmup, level, tune_max, force_shape=None):
@@ -151,10 +166,14 @@ def run_precision(model, precision, order, steps, warmup, level, tune_max, force
     phases, nt = sim.timers()
     ms_step = wall / steps * 1e3
     inter = float(n_act_sum) * model.n
-    log("[%s] %d steps: %.1f ms/step, %.4e interactions/s; phases (ms/step) %s"
-        % (precision, steps, ms_step, inter / wall, {k: round(v / nt, 3) for k, v in phases.items()}))
+    used = sim.last_launch()
+    log("[%s] %d steps: %.1f ms/step, %.4e interactions/s; phases (ms/step) %s; force launched as ni %d, "
+        "block %d, %d splits, jpath %d" % (precision, steps, ms_step, inter / wall,
+                                          {k: round(v / nt, 3) for k, v in phases.items()}, *used))
+    if shape is not None:
+        shape["used"] = {"ni": used[0], "block": used[1], "n_split": used[2], "jpath": used[3]}
     return sim, {"ms_per_step": ms_step, "interactions_per_s": inter / wall, "n_act_per_step": n_act_sum / steps,
-                 "phase_ms_per_step": {k: v / nt for k, v in phases.items()}, "launch": shape}
+                 "phase_ms_per_step": {k: v / nt for k, v in phases.items()}, "launch": shape, "used": used}
 
 
 def cpu_baseline_and_error(model, sims, order, target_s):
@@ -200,6 +219,7 @@ def cpu_baseline_and_error(model, sims, order, target_s):
         errors[prec] = e
         log("[cpu] %s error vs oracle: %s" % (prec, {k: "%.2e/%.2e" % (v["rms"], v["max"]) for k, v in e.items()}))
     base = {"value": rows * n / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "%d random active rows x all %d j-particles of the same 6th-order step (FP64 C oracle, "
                       "OpenMP over rows), %.1f s" % (rows, n, dt)}
     return base, errors, rows
@@ -564,13 +584,13 @@ def run_neighbour(args):
             rate = float(n_act) * n / (ms_nb * 1e-3)
             peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
             row = {"n": n, "n_act": n_act, "precision": prec, "ms_nb": ms_nb, "ms_force": ms_f,
-                   "interactions_per_s": rate, "frac_of_peak_43flops": 43 * rate / 1e12 / peak,
+                   "interactions_per_s": rate, "frac_of_peak": FLOPS_PER_INTERACTION[4] * rate / 1e12 / peak,
                    "nb_mean": float(cnt.mean()), "nb_max": int(cnt.max()),
                    "irr_plus_reg_vs_full_max": float(tot.max())}
             table.append(row)
-            log("[nb] n %d n_act %6d %-5s: split force + lists %.4f ms (%.3e int/s, %.1f%% of peak at 43 flops), "
+            log("[nb] n %d n_act %6d %-5s: split force + lists %.4f ms (%.3e int/s, %.1f%% of peak at 41 flops), "
                 "plain force %.4f ms (%.2fx); neighbours mean %.1f max %d; |irr + reg - full| / |full| max %.1e"
-                % (n, n_act, prec, ms_nb, rate, 100 * row["frac_of_peak_43flops"], ms_f, ms_nb / ms_f,
+                % (n, n_act, prec, ms_nb, rate, 100 * row["frac_of_peak"], ms_f, ms_nb / ms_f,
                    cnt.mean(), cnt.max(), row["irr_plus_reg_vs_full_max"]))
             sim.close()
             del sim
@@ -884,7 +904,7 @@ def main():
     # (fixed here so that the timed kernel is the profiled one); "" = autotune
     ap.add_argument("--force-shape-mixed", default="2,256,16,2",
                     help="ni,block,n_split,jpath of the MIXED force ('' = autotune up to --tune-max)")
-    ap.add_argument("--force-shape-fp64", default="2,128,32,1",
+    ap.add_argument("--force-shape-fp64", default="2,128,16,1",
                     help="ni,block,n_split,jpath of the FP64 force ('' = autotune up to --tune-max)")
     ap.add_argument("--tune-max", type=int, default=65536,
                     help="autotune the force launch up to this n_act before timing (0 = untuned defaults)")
@@ -951,15 +971,18 @@ def main():
     n_act = int(round(mixed["n_act_per_step"]))
     flops_launch = FLOPS_PER_INTERACTION[args.order] * float(n_act) * n
     achieved = flops_launch / (force_ms * 1e-3) / 1e12
-    traffic = read_traffic(n_act, n, mixed["launch"])
+    traffic = read_traffic(n_act, n, mixed["used"])
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": kernel_name(mixed["launch"], args.order),
+                "kernel": kernel_name(mixed["used"], args.order),
                 "launch": mixed["launch"],
                 "flops_per_interaction": FLOPS_PER_INTERACTION[args.order],
+                "flops_convention": "minimal operation list without the potential (add/sub/mul 1, FMA 2, rsqrt 1); "
+                                    "%d with the potential" % FLOPS_WITH_POT[args.order],
                 "force_ms_per_launch": round(force_ms, 3),
-                "frac_literature_97_flops": round(achieved * FLOPS_LITERATURE[args.order]
-                                                  / FLOPS_PER_INTERACTION[args.order] / PEAK_FP32_TFLOPS, 4)}
+                "frac_literature_%d_flops" % FLOPS_LITERATURE[args.order]:
+                    round(achieved * FLOPS_LITERATURE[args.order] / FLOPS_PER_INTERACTION[args.order]
+                          / PEAK_FP32_TFLOPS, 4)}
 
     cpu, errors, rows = None, None, 0
     if not args.no_cpu_baseline:
@@ -982,18 +1005,25 @@ def main():
         "data": "synthetic",
         "config": {"workload": "King W0=7 cluster, n=%d, 6th-order Hermite block step with all n particles "
                                "active (one shared level k=%d), MIXED pairwise force" % (n, args.level),
-                   "n": n, "order": args.order, "precision": "mixed", "n_act": n_act, "eps": 1e-4,
+                   "n": n, "order": args.order, "precision": "mixed",
+                   "accumulation": "double-single position and velocity differences, FP32 pair arithmetic, FP32 "
+                                   "partial sums over chunks of 128 j added into FP64 accumulators (the chunked "
+                                   "mixed mode)",
+                   "n_act": n_act, "eps": 1e-4,
                    "interactions_per_step": float(n_act) * n, "interaction_count": "n_act * n (self pair counted)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "force_only": {"mixed_interactions_per_s": float(n_act) * n / (force_ms * 1e-3),
                        "fp64_interactions_per_s": float(n_act) * n / (fp64_force_ms * 1e-3),
                        "mixed_over_fp64": fp64_force_ms / force_ms,
-                       "mixed_gflops_80": achieved * 1e3,
-                       "mixed_gflops_97": FLOPS_LITERATURE[args.order] * float(n_act) * n / (force_ms * 1e-3) / 1e9},
+                       "mixed_gflops": achieved * 1e3,
+                       "mixed_gflops_literature": FLOPS_LITERATURE[args.order] * float(n_act) * n
+                       / (force_ms * 1e-3) / 1e9},
         "fp64": {"value": fp64["interactions_per_s"], "ms_per_step": fp64["ms_per_step"],
                  "phase_ms_per_step": fp64["phase_ms_per_step"],
-                 "force_tflops_80": FLOPS_PER_INTERACTION[args.order] * float(n_act) * n / (fp64_force_ms * 1e-3) / 1e12,
+                 "force_launch_used": {"ni": fp64["used"][0], "block": fp64["used"][1], "n_split": fp64["used"][2],
+                                       "jpath": fp64["used"][3]},
+                 "force_tflops": FLOPS_PER_INTERACTION[args.order] * float(n_act) * n / (fp64_force_ms * 1e-3) / 1e12,
                  "frac_of_fp64_peak": FLOPS_PER_INTERACTION[args.order] * float(n_act) * n
                  / (fp64_force_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
         "phase_ms_per_step": mixed["phase_ms_per_step"],

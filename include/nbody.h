@@ -5,11 +5,11 @@
  * softened Newtonian gravity between all particles, integrated with a
  * 4th-, 6th- or 8th-order Hermite predictor-corrector scheme and individual
  * hierarchical (power-of-two) block time steps, with the force evaluated in
- * mixed FP32/FP64 precision (paper: Fig. 1 and Fig. 5 captions, "mixed
- * (fp32 + fp64) precision").  The paper names the scheme without formulas;
- * the library follows the standard published ones: the force-derivative
- * recursion, corrector and generalised time-step criterion of Nitadori &
- * Makino (2008), and Aarseth's criterion for order 4.
+ * mixed FP32/FP64 precision (paper: Fig. 1 and Fig. 5 captions).  The paper
+ * names the scheme without formulas; the library follows the standard
+ * published ones: the force-derivative recursion, corrector and generalised
+ * time-step criterion of Nitadori & Makino (2008), and Aarseth's criterion
+ * for order 4.
  *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers owned by the caller, unless the
@@ -201,8 +201,9 @@ nbody_status nbody_set_fusion(nbody_ctx *ctx, int32_t enable);
  * row whose list was cut (nb_count[q] > max_nb) gets NaN in acc_irr and
  * jrk_irr; its regular part is complete.  h2 (DEVICE) [n_act] FP64.  max_nb
  * in [0, 4096]; nb_list may be NULL when max_nb is 0 (regular part and counts
- * only).  Uses the context's force scratch: n_act * (13 + max_nb) must stay
- * below 2^21 * 26 (about 5.4e7), else NBODY_E_INVALID (call in pieces).
+ * only).  Uses the context's force scratch of R = max(2^21, min(16 n, 2^26))
+ * rows: n_act * (13 + max_nb) must stay below 26 R, else NBODY_E_INVALID
+ * (call in pieces).
  * The sum orders are fixed, so reruns are bitwise identical. */
 nbody_status nbody_force_block_nb(nbody_ctx *ctx, int64_t n_act, const int32_t *act_idx, const double *h2,
                                   int32_t max_nb, double *acc_irr, double *jrk_irr, double *acc_reg,
@@ -260,10 +261,13 @@ nbody_status nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
  * (0 = default for the precision, 1 = wave-uniform scalar loads, 2 = LDS
  * tiles, 3 = wave j-split for small active sets: 1, 4 or 16 active rows per
  * 64-lane workgroup, each row's j range spread over 64, 16 or 4 lanes and
- * folded across them; ni and block are ignored).  A shape set here is used for every later force call (it replaces
- * an autotuned table).  Without either, a call uses the wave j-split kernel
- * for n_act <= 32, else ni = 1, the narrowest workgroup of 64, 128 or 256
- * lanes that holds n_act, and the default split.
+ * folded across them; ni and block are ignored).  A shape set here is used
+ * for every later force call (it replaces an autotuned table).  Without
+ * either, a call uses the wave j-split kernel for n_act <= 32, else ni = 1,
+ * the narrowest workgroup of 64, 128 or 256 lanes that holds n_act, and the
+ * default split.  A call lowers n_split where it exceeds what the partial-sum
+ * scratch holds (n_act * n_split <= max(2^21, min(16 n, 2^26))) or gives
+ * splits shorter than 128 j; nbody_get_last_launch tells the shape used.
  * Results do not depend on ni, block or jpath; they depend on n_split only
  * through the FP64 summation order (and, in MIXED mode, where the FP32 chunks
  * start). */
@@ -286,6 +290,12 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int64_t max_n_act, int32_t reps);
  * *rows = rows in the table (0 when not tuned). */
 nbody_status nbody_get_tuning(nbody_ctx *ctx, int32_t max_rows, int64_t *n_act, int32_t *shape, double *ms,
                               int32_t *rows);
+
+/* The launch shape of the last force kernel this context ran (any entry
+ * point that computes forces; HOST out[4]): ni, block, n_split (as launched,
+ * after the bounds of nbody_set_launch), jpath (1, 2 or 3).  Zeros before the
+ * first force call. */
+nbody_status nbody_get_last_launch(nbody_ctx *ctx, int32_t out[4]);
 
 /* Phase timers of nbody_step, measured with HIP events on the context's
  * stream.  nbody_set_timing(ctx, 1) creates the events and starts

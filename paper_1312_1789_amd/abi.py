@@ -40,7 +40,7 @@ EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
     "nbody_force_block", "nbody_predict_force", "nbody_set_fusion", "nbody_force_block_nb", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
-    "nbody_autotune", "nbody_get_tuning",
+    "nbody_autotune", "nbody_get_tuning", "nbody_get_last_launch",
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
     "nbody_batch_set_end", "nbody_batch_step", "nbody_batch_capture", "nbody_batch_replay", "nbody_batch_poll",
     "nbody_batch_last_step", "nbody_batch_energy", "nbody_batch_get_stats", "nbody_batch_set_launch",
@@ -107,6 +107,7 @@ def lib():
             "nbody_autotune": [P, I64, C.c_int32],
             "nbody_get_tuning": [P, C.c_int32, C.POINTER(I64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                  C.POINTER(C.c_int32)],
+            "nbody_get_last_launch": [P, C.POINTER(C.c_int32)],
             "nbody_batch_workspace_size": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), C.POINTER(C.c_size_t)],
             "nbody_batch_create": [C.POINTER(nbody_config), C.c_int32, C.POINTER(I64), P, C.c_size_t, P,
                                    C.POINTER(P)],
@@ -269,6 +270,13 @@ def nbody_get_tuning(ctx: int):
     _check(lib().nbody_get_tuning(C.c_void_p(ctx), k, na, sh, ms, C.byref(rows)), "nbody_get_tuning")
     return [(int(na[r]), int(sh[4 * r]), int(sh[4 * r + 1]), int(sh[4 * r + 2]), int(sh[4 * r + 3]), float(ms[r]))
             for r in range(rows.value)]
+
+
+def nbody_get_last_launch(ctx: int):
+    """(ni, block, n_split, jpath) of the last force kernel the context ran."""
+    out = (C.c_int32 * 4)()
+    _check(lib().nbody_get_last_launch(C.c_void_p(ctx), out), "nbody_get_last_launch")
+    return tuple(int(v) for v in out)
 
 
 PHASES = ("schedule", "host_roundtrip", "predict", "force", "correct")

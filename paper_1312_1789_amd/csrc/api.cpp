@@ -79,6 +79,7 @@ nb::ForceArgs force_args(nbody_ctx *ctx, const void *rec, int64_t n_act, const i
     a.out[3] = crk;
     a.out[4] = pot;
     a.part = ws_at<double>(ctx, ctx->lay.part);
+    a.part_rows = nb::part_rows_for(ctx->cfg.n);
     if (ctx->manual) {
         a.ni = ctx->ni;
         a.block = ctx->block;
@@ -108,8 +109,7 @@ nbody_status run_force(nbody_ctx *ctx, int order, int precision, const void *rec
                        const int32_t *act, double *acc, double *jrk, double *snp, double *crk, double *pot)
 {
     const nb::ForceArgs a = force_args(ctx, rec, n_act, act, acc, jrk, snp, crk, pot);
-    int used = 0;
-    NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &used));
+    NB_HIP(nb::launch_force(order, precision, a, ctx->stream, &ctx->last_shape));
     ctx->stats.interactions += double(n_act) * double(ctx->cfg.n);
     return NBODY_OK;
 }
@@ -126,7 +126,6 @@ nbody_status run_predict_force(nbody_ctx *ctx, const nbody_state *st, int64_t t,
     const nb::ForceArgs a = force_args(ctx, ctx->ws + ctx->lay.rec, n_act, act, acc, jrk, snp, crk, pot);
     const bool f = ctx->fuse && a.jpath == 3;
     if (fused) *fused = f;
-    int used = 0;
     if (f) {
         nb::PredIn in{};
         in.m = st->m;
@@ -136,11 +135,11 @@ nbody_status run_predict_force(nbody_ctx *ctx, const nbody_state *st, int64_t t,
         in.t_tick = st->t_tick;
         in.t = t;
         ctx->predicted = false;   // the records are stale from here on
-        NB_HIP(nb::launch_force_pred(c.order, c.precision, a, in, ctx->stream, &used));
+        NB_HIP(nb::launch_force_pred(c.order, c.precision, a, in, ctx->stream, &ctx->last_shape));
     } else {
         NB_HIP(nb::launch_predict(c.order, c.precision, c.n, *st, t, ctx->ws + ctx->lay.rec, ctx->stream));
         ctx->predicted = true;
-        NB_HIP(nb::launch_force(c.order, c.precision, a, ctx->stream, &used));
+        NB_HIP(nb::launch_force(c.order, c.precision, a, ctx->stream, &ctx->last_shape));
     }
     ctx->stats.interactions += double(n_act) * double(c.n);
     return NBODY_OK;
@@ -213,7 +212,7 @@ Layout make_layout(const nbody_config &c)
     const size_t n = size_t(c.n);
     const size_t nb = (n + kSchedChunk - 1) / kSchedChunk;
     L.rec = take(n * size_t(record_bytes(c.order, c.precision)));
-    L.part = take(size_t(kPartEntries) * kMaxComp * sizeof(double));
+    L.part = take(size_t(part_rows_for(c.n)) * kMaxComp * sizeof(double));
     L.force = take(12 * n * sizeof(double));
     L.act = take(n * sizeof(int32_t));
     L.sched = take(nb * (2 * sizeof(int64_t) + sizeof(int32_t)));
@@ -265,6 +264,7 @@ nbody_status nbody_create(const nbody_config *cfg, void *workspace, size_t bytes
     ctx->manual = false;
     ctx->tuned = false;
     ctx->n_tune = 0;
+    ctx->last_shape = nb::UsedShape{0, 0, 0, 0};
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess) e = hipMemsetAsync(scalars(ctx), 0, sizeof(nb::DevScalars), ctx->stream);
@@ -370,12 +370,13 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int64_t max_n_act, int32_t reps)
                 for (int jpath : {1, 2, 3}) {
                     // the wave j-split kernel ignores ni and block, and serves small active sets
                     if (jpath == 3 && (ni != 1 || block != 64 || na > 64)) continue;
-                    const int base = nb::auto_split_path(n, na, ni, block, jpath);
+                    const int64_t prow = nb::part_rows_for(n);
+                    const int base = nb::auto_split_path(n, na, ni, block, jpath, prow);
                     int prev = -1;
                     for (int mult : {1, 2, 4}) {   // splits base / 2, base, base * 2
                         int sp = mult == 1 ? base / 2 : (mult == 2 ? base : base * 2);
                         sp = sp < 1 ? 1 : (sp > 65535 ? 65535 : sp);
-                        if (int64_t(sp) * na > nb::kPartEntries) sp = int(nb::kPartEntries / na);
+                        if (int64_t(sp) * na > prow) sp = int(prow / na);
                         if (sp == prev) continue;
                         prev = sp;
                         nb::ForceArgs a{};
@@ -391,6 +392,7 @@ nbody_status nbody_autotune(nbody_ctx *ctx, int64_t max_n_act, int32_t reps)
                         a.out[3] = c.order >= 8 ? F + 9 * n : nullptr;
                         a.out[4] = nullptr;
                         a.part = ws_at<double>(ctx, ctx->lay.part);
+                        a.part_rows = prow;
                         a.ni = ni;
                         a.block = block;
                         a.n_split = sp;
@@ -441,6 +443,16 @@ nbody_status nbody_get_tuning(nbody_ctx *ctx, int32_t max_rows, int64_t *n_act, 
         if (ms) ms[k] = ctx->tune[k].ms;
     }
     *rows = ctx->tuned ? ctx->n_tune : 0;
+    return NBODY_OK;
+}
+
+nbody_status nbody_get_last_launch(nbody_ctx *ctx, int32_t out[4])
+{
+    if (!ctx || !out) return fail(NBODY_E_INVALID, "ctx and out are required");
+    out[0] = ctx->last_shape.ni;
+    out[1] = ctx->last_shape.block;
+    out[2] = ctx->last_shape.n_split;
+    out[3] = ctx->last_shape.jpath;
     return NBODY_OK;
 }
 
@@ -543,7 +555,7 @@ nbody_status nbody_force_block_nb(nbody_ctx *ctx, int64_t n_act, const int32_t *
     if (!nb_count || (reinterpret_cast<uintptr_t>(nb_count) & 3u)) return fail(NBODY_E_INVALID, "nb_count must be non-NULL, 4-byte aligned");
     if (max_nb > 0 && (!nb_list || (reinterpret_cast<uintptr_t>(nb_list) & 3u)))
         return fail(NBODY_E_INVALID, "nb_list must be non-NULL, 4-byte aligned when max_nb > 0");
-    const int64_t scratch = int64_t(nb::kPartEntries) * nb::kMaxComp * int64_t(sizeof(double));
+    const int64_t scratch = nb::part_rows_for(c.n) * nb::kMaxComp * int64_t(sizeof(double));
     const int sp = nb::nb_split(c.n, n_act, max_nb, scratch, 0);
     if (sp < 1)
         return fail(NBODY_E_INVALID, "n_act * (13 + max_nb) = %lld exceeds the scratch (%lld); call with fewer rows",

@@ -377,7 +377,7 @@ int record_bytes(int order, int precision)
 // Number of j-splits: enough waves to cover every SIMD several times when the
 // active set is small, bounded by the partial-sum scratch and by keeping at
 // least 256 j per split.
-int auto_split(int64_t n, int64_t n_act, int ni, int block)
+int auto_split(int64_t n, int64_t n_act, int ni, int block, int64_t part_rows)
 {
     const int64_t per_block = int64_t(block) * ni;
     const int64_t tiles = (n_act + per_block - 1) / per_block;
@@ -385,16 +385,16 @@ int auto_split(int64_t n, int64_t n_act, int ni, int block)
     const int64_t target_waves = 256 * 4 * 8;   // CUs x SIMDs x waves per SIMD
     int64_t sp = (target_waves + waves - 1) / waves;
     const int64_t max_by_n = n / kMixedChunk > 0 ? n / kMixedChunk : 1;   // splits of at least one FP32 chunk
-    const int64_t max_by_part = kPartEntries / (n_act > 0 ? n_act : 1);
+    const int64_t max_by_part = part_rows / (n_act > 0 ? n_act : 1);
     if (sp > max_by_n) sp = max_by_n;
     if (sp > max_by_part) sp = max_by_part;
     if (sp > 65535) sp = 65535;
     return sp < 1 ? 1 : int(sp);
 }
 
-int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath)
+int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath, int64_t part_rows)
 {
-    if (jpath != 3) return auto_split(n, n_act, ni, block);
+    if (jpath != 3) return auto_split(n, n_act, ni, block, part_rows);
     // kernel C: one 64-lane workgroup per 1, 4 or 16 rows and split.  Split
     // counts giving about 512, 1024 and 2048 workgroups were the fastest on
     // MI355X (n = 2^17 and 2^20, orders 6 and 8, with and without the
@@ -405,18 +405,18 @@ int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath)
     const int64_t target = rw == 1 ? 512 : (rw == 4 ? 1024 : 2048);
     int64_t sp = (target + tiles - 1) / tiles;
     const int64_t max_by_n = n / kMixedChunk > 0 ? n / kMixedChunk : 1;
-    const int64_t max_by_part = kPartEntries / (n_act > 0 ? n_act : 1);
+    const int64_t max_by_part = part_rows / (n_act > 0 ? n_act : 1);
     if (sp > max_by_n) sp = max_by_n;
     if (sp > max_by_part) sp = max_by_part;
     if (sp > 65535) sp = 65535;
     return sp < 1 ? 1 : int(sp);
 }
 
-void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int *n_split,
-                 int64_t *j_chunk)
+void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int64_t part_rows,
+                 int *n_split, int64_t *j_chunk)
 {
-    int sp = n_split_req > 0 ? n_split_req : auto_split_path(n, n_act, ni, block, jpath);
-    if (int64_t(sp) * n_act > kPartEntries) sp = int(kPartEntries / n_act);
+    int sp = n_split_req > 0 ? n_split_req : auto_split_path(n, n_act, ni, block, jpath, part_rows);
+    if (n_act > 0 && int64_t(sp) * n_act > part_rows) sp = int(part_rows / n_act);
     if (sp < 1) sp = 1;
     // split length: a multiple of the MIXED chunk so chunks never straddle splits
     int64_t jc = (n + sp - 1) / sp;
@@ -432,15 +432,15 @@ hipError_t launch_split_reduce_sf(int order, const ForceArgs &a, int n_split, hi
     return launch_reduce<8, true>(a, n_split, s);
 }
 
-hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split)
+hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, UsedShape *used)
 {
     Shape sh{};
     sh.ni = (a.ni == 2) ? 2 : 1;
     sh.block = (a.block == 64 || a.block == 128) ? a.block : 256;
     // j path: FP64 reads j records from SGPRs, the FP32 modes from LDS
     sh.jpath = a.jpath >= 1 && a.jpath <= 3 ? a.jpath : (precision == NBODY_FP64 ? 1 : 2);
-    split_shape(a.n, a.n_act, a.n_split, sh.ni, sh.block, sh.jpath, &sh.n_split, &sh.j_chunk);
-    if (used_split) *used_split = sh.n_split;
+    split_shape(a.n, a.n_act, a.n_split, sh.ni, sh.block, sh.jpath, a.part_rows, &sh.n_split, &sh.j_chunk);
+    if (used) *used = UsedShape{sh.jpath == 3 ? 1 : sh.ni, sh.jpath == 3 ? 64 : sh.block, sh.n_split, sh.jpath};
     switch (order) {
     case 4: return run_prec<4>(precision, a, s, sh);
     case 6: return run_prec<6>(precision, a, s, sh);

@@ -194,12 +194,12 @@ hipError_t run_prec(int precision, const ForceArgs &a, const PredIn &in, hipStre
 }  // namespace
 
 hipError_t launch_force_pred(int order, int precision, const ForceArgs &a, const PredIn &in, hipStream_t s,
-                             int *used_split)
+                             UsedShape *used)
 {
     int n_split = 1;
     int64_t j_chunk = 0;
-    split_shape(a.n, a.n_act, a.n_split, 1, 64, 3, &n_split, &j_chunk);
-    if (used_split) *used_split = n_split;
+    split_shape(a.n, a.n_act, a.n_split, 1, 64, 3, a.part_rows, &n_split, &j_chunk);
+    if (used) *used = UsedShape{1, 64, n_split, 3};
     switch (order) {
     case 4: return run_prec<4>(precision, a, in, s, n_split, j_chunk);
     case 6: return run_prec<6>(precision, a, in, s, n_split, j_chunk);

@@ -29,7 +29,15 @@ constexpr int kSchedBlock = 256;            // threads per scheduler block
 constexpr int kSchedPerThread = 4;          // particles per scheduler thread
 constexpr int kSchedChunk = kSchedBlock * kSchedPerThread;
 constexpr int kMixedChunk = 128;            // FP32 partial-sum length in MIXED mode
-constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act_pad * n_split)
+constexpr int64_t kPartEntries = int64_t(1) << 21;  // j-split partial rows (n_act * n_split), at least
+// Rows of j-split partial sums a context keeps (n_act * n_split <= rows): 16 per
+// particle, so that an all-active force call can still take 16 splits, at
+// least kPartEntries and at most 2^26 (7 GB of doubles).
+inline int64_t part_rows_for(int64_t n)
+{
+    const int64_t r = 16 * n;
+    return r < kPartEntries ? kPartEntries : (r > (int64_t(1) << 26) ? (int64_t(1) << 26) : r);
+}
 constexpr int kMaxComp = 13;                // acc3 + jerk3 + snap3 + crackle3 + pot
 constexpr int kMaxNeighbours = 4096;        // neighbour-list capacity per row, at most
 
@@ -56,7 +64,7 @@ int record_bytes(int order, int precision);
 // Offsets of the sub-buffers inside the caller's workspace (bytes).
 struct Layout {
     size_t rec;        // predicted records, n * record_bytes
-    size_t part;       // j-split partial sums, kPartEntries * kMaxComp doubles
+    size_t part;       // j-split partial sums, part_rows_for(n) * kMaxComp doubles
     size_t force;      // step force outputs, kMaxComp-1 rows of n doubles ([12][n])
     size_t act;        // active indices, n int32
     size_t sched;      // scheduler per-block scratch (min ticks, counts, offsets)
@@ -87,17 +95,24 @@ struct ForceArgs {
     int64_t n_hard;         // already n when eps2 == 0
     double *out[5];         // acc, jrk, snp, crk, pot ([3][n_act] / [n_act]); may be null
     double *part;           // partial-sum scratch
+    int64_t part_rows;      // its capacity in rows of kMaxComp doubles (n_act * n_split <= part_rows)
     int ni, block, n_split; // launch shape (n_split 0 = auto)
     int jpath;              // 0 auto, 1 scalar loads, 2 LDS tiles
 };
 
-hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, int *used_split);
+// The launch shape a force call ran with (n_split after the scratch bound).
+struct UsedShape {
+    int ni, block, n_split, jpath;
+};
+
+hipError_t launch_force(int order, int precision, const ForceArgs &a, hipStream_t s, UsedShape *used);
 
 // j-splits and split length (a multiple of the MIXED chunk) of a force launch:
-// n_split_req > 0 is taken as given (bounded by the partial-sum scratch),
-// 0 chooses from n_act and the shape.
-void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int *n_split,
-                 int64_t *j_chunk);
+// n_split_req > 0 is taken as given, bounded by the partial-sum scratch
+// (n_act * n_split <= part_rows) and by the split length (at least one MIXED
+// chunk); 0 chooses from n_act and the shape.
+void split_shape(int64_t n, int64_t n_act, int n_split_req, int ni, int block, int jpath, int64_t part_rows,
+                 int *n_split, int64_t *j_chunk);
 
 // Fixed-order sum of n_split partial results in a.part into a.out.
 // the split reduction for partial sums in part[component][row][split] (wave j-split kernels)
@@ -115,7 +130,7 @@ struct PredIn {
 // loads: a.rec is not read; the j-particles and the active i-particles are
 // predicted from `in` to in.t, exactly as the predictor kernel writes them.
 hipError_t launch_force_pred(int order, int precision, const ForceArgs &a, const PredIn &in, hipStream_t s,
-                             int *used_split);
+                             UsedShape *used);
 
 // Force split by neighbour spheres (order-4 terms) with the neighbour lists.
 struct NbArgs {
@@ -140,10 +155,10 @@ hipError_t launch_force_nb(int precision, const NbArgs &a, int n_split, hipStrea
 
 // j-splits that give about 8 waves per SIMD for n_act rows in workgroups of
 // `block` lanes with ni rows per lane (the default when n_split is 0).
-int auto_split(int64_t n, int64_t n_act, int ni, int block);
+int auto_split(int64_t n, int64_t n_act, int ni, int block, int64_t part_rows);
 // The default split of a j path (jpath 3, the wave j-split kernel, sizes its
 // own workgroups: 1, 4 or 16 active rows in 64 lanes).
-int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath);
+int auto_split_path(int64_t n, int64_t n_act, int ni, int block, int jpath, int64_t part_rows);
 
 // One row of the force-launch table filled by nbody_autotune.
 struct TuneRow {
@@ -218,6 +233,7 @@ struct nbody_ctx {
     bool predicted;
     bool fuse;                        // predictor folded into the wave j-split force (nbody_set_fusion)
     int ni, block, n_split, jpath;   // launch shape fixed by nbody_set_launch (when manual)
+    nb::UsedShape last_shape;         // shape of the last force launch (nbody_get_last_launch)
     bool manual;
     bool tuned;                       // tune[] filled by nbody_autotune
     int n_tune;

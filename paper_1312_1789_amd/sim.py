@@ -80,6 +80,10 @@ class Simulation:
     def tuning(self):
         return abi.nbody_get_tuning(self.ctx)
 
+    def last_launch(self):
+        """(ni, block, n_split, jpath) of the last force kernel run."""
+        return abi.nbody_get_last_launch(self.ctx)
+
     def set_timing(self, enable: bool = True):
         abi.nbody_set_timing(self.ctx, enable)
 
