@@ -176,6 +176,27 @@ nbody_status nbody_predict_force(nbody_ctx *ctx, const nbody_state *state, int64
                                  const int32_t *act_idx, double *acc, double *jrk, double *snp, double *crk,
                                  double *pot);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the work of
+ * nbody_predict_force with fusion on and the wave j-split kernel (jpath 3,
+ * default split), without a context or workspace.  cfg: as for
+ * nbody_create (host); state (host struct of DEVICE pointers): m, x, v, d[],
+ * t_tick are read, level is not; t_tick: the time every particle is
+ * predicted to (>= each particle's time); act_idx, outputs, results: as
+ * nbody_predict_force, bit for bit equal to it when that call runs the same
+ * kernel and split (a context set to nbody_set_launch(ctx, 1, 64, 0, 3)).
+ * stream: a hipStream_t of the current device (NULL = default stream); the
+ * call is asynchronous on it.  1 <= n_act <= 1024 (0 does nothing), else
+ * NBODY_E_INVALID: the j-split partial sums live in a static device array of
+ * 65536 rows x 13 doubles (6.8 MB per GPU, held until the process ends),
+ * whose device address is looked up once per device.  The call allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other streams, other host threads) race.  Each call writes every
+ * partial sum it reads, so nothing needs clearing between calls. */
+nbody_status nbody_predict_force_noalloc(const nbody_config *cfg, const nbody_state *state, int64_t t_tick,
+                                         int64_t n_act, const int32_t *act_idx, double *acc, double *jrk,
+                                         double *snp, double *crk, double *pot, void *stream);
+
 /* enable = 1 (default): nbody_predict_force, nbody_step and nbody_run fold
  * the predictor into the wave j-split force kernel; 0: they always run the
  * predictor kernel and then the force kernel.  Results are the same. */

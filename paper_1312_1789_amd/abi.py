@@ -38,7 +38,7 @@ def effective_dt_rule(order: int, precision: int, dt_rule: int = 0) -> int:
 #: every symbol the header declares
 EXPORTS = (
     "nbody_workspace_size", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
-    "nbody_force_block", "nbody_predict_force", "nbody_set_fusion", "nbody_force_block_nb", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
+    "nbody_force_block", "nbody_predict_force", "nbody_predict_force_noalloc", "nbody_set_fusion", "nbody_force_block_nb", "nbody_correct", "nbody_schedule", "nbody_step", "nbody_run", "nbody_energy",
     "nbody_get_predicted", "nbody_get_stats", "nbody_set_launch", "nbody_set_timing", "nbody_get_timers",
     "nbody_autotune", "nbody_get_tuning", "nbody_get_last_launch",
     "nbody_batch_workspace_size", "nbody_batch_create", "nbody_batch_destroy", "nbody_batch_init",
@@ -92,6 +92,8 @@ def lib():
             "nbody_predict": [P, C.POINTER(nbody_state), I64],
             "nbody_force_block": [P, I64, P, P, P, P, P, P],
             "nbody_predict_force": [P, C.POINTER(nbody_state), I64, I64, P, P, P, P, P, P],
+            "nbody_predict_force_noalloc": [C.POINTER(nbody_config), C.POINTER(nbody_state), I64, I64, P, P, P, P,
+                                            P, P, P],
             "nbody_set_fusion": [P, C.c_int32],
             "nbody_force_block_nb": [P, I64, P, P, C.c_int32, P, P, P, P, P, P],
             "nbody_correct": [P, C.POINTER(nbody_state), I64, P, I64, P, P, P, P],
@@ -182,6 +184,14 @@ def nbody_predict_force(ctx: int, st: nbody_state, t_tick: int, n_act: int, act_
     P = C.c_void_p
     _check(lib().nbody_predict_force(P(ctx), C.byref(st), int(t_tick), int(n_act), P(act_idx), P(acc), P(jrk),
                                      P(snp or None), P(crk or None), P(pot or None)), "nbody_predict_force")
+
+
+def nbody_predict_force_noalloc(cfg: nbody_config, st: nbody_state, t_tick: int, n_act: int, act_idx: int, acc: int,
+                                jrk: int, snp: int = 0, crk: int = 0, pot: int = 0, stream: int = 0) -> None:
+    P = C.c_void_p
+    _check(lib().nbody_predict_force_noalloc(C.byref(cfg), C.byref(st), int(t_tick), int(n_act), P(act_idx), P(acc),
+                                             P(jrk), P(snp or None), P(crk or None), P(pot or None),
+                                             P(stream or None)), "nbody_predict_force_noalloc")
 
 
 def nbody_force_block_nb(ctx: int, n_act: int, act_idx: int, h2: int, max_nb: int, acc_irr: int, jrk_irr: int,

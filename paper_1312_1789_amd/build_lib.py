@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["force.hip", "force_pred.hip", "force_nb.hip", "pn.hip", "integrate.hip", "batch.hip", "api.cpp", "batch_api.cpp"]
+SOURCES = ["force.hip", "force_pred.hip", "force_nb.hip", "pn.hip", "integrate.hip", "batch.hip", "api.cpp", "batch_api.cpp",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
