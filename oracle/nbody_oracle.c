@@ -26,8 +26,8 @@
  *     particles inside a neighbour sphere and over the rest, with the
  *     neighbour list;
  *   - post-Newtonian corrections between black holes (the paper's relativistic
- *     corrections for its black-hole binaries, Introduction): the 1PN and
- *     2.5PN terms of the two-body relative acceleration in harmonic
+ *     corrections for its black-hole binaries, Introduction): the 1PN, 2PN
+ *     and 2.5PN terms of the two-body relative acceleration in harmonic
  *     coordinates (Blanchet 2014, Living Rev. Relativ. 17, 2, the A and B
  *     coefficients), added pairwise to the hard particles.
  * Build: gcc -O2 -ffp-contract=off -fopenmp, so rounding follows the source.
@@ -58,7 +58,7 @@ typedef struct {
                          2 = its order-4 form (reads a .. a^(3) only) */
     double c_light;   /* speed of light in the model's units; > 0 turns the
                          post-Newtonian terms of hard pairs on */
-    int pn_terms;     /* which: 1 = 1PN, 4 = 2.5PN (radiation reaction), 5 = both */
+    int pn_terms;     /* which, a sum of: 1 = 1PN, 2 = 2PN, 4 = 2.5PN (radiation reaction) */
 } oracle_config;
 
 /* Particle state.  d[k] is the k-th derivative of the acceleration a^(k)
@@ -221,6 +221,13 @@ int oracle_force_nb(const oracle_config *c, int64_t n, const double *m, const do
  * relative acceleration is  -(M / r^2) [(1 + A) n + B v]  with
  *   A_1PN   = ( -3/2 nu rdot^2 + (1 + 3 nu) v^2 - 2 (2 + nu) M / r ) / c^2
  *   B_1PN   = ( -2 (2 - nu) rdot ) / c^2
+ *   A_2PN   = ( 15/8 nu rdot^4 - 45/8 nu^2 rdot^4 - 9/2 nu rdot^2 v^2
+ *               + 6 nu^2 rdot^2 v^2 + 3 nu v^4 - 4 nu^2 v^4
+ *               + (M / r) (-2 rdot^2 - 25 nu rdot^2 - 2 nu^2 rdot^2
+ *                          - 13/2 nu v^2 + 2 nu^2 v^2)
+ *               + (M / r)^2 (9 + 87/4 nu) ) / c^4
+ *   B_2PN   = ( 9/2 nu rdot^3 + 3 nu^2 rdot^3 - 15/2 nu rdot v^2
+ *               - 2 nu^2 rdot v^2 + (M / r) (2 + 41/2 nu + 4 nu^2) rdot ) / c^4
  *   A_2.5PN = -8/5 nu (M / r) rdot ( 17/3 M / r + 3 v^2 ) / c^5
  *   B_2.5PN =  8/5 nu (M / r) ( 3 M / r + v^2 ) / c^5
  * (the Newtonian part is the pair term of the direct sum).  Body 1 takes
@@ -312,6 +319,36 @@ void oracle_pn_rel_derivs(double M, double nu, double c, int terms, const double
                                ts_scl(-2.0 * (2.0 + nu), Mr));
         A = ts_add(A, ts_scl(1.0 / c2, a1));
         B = ts_add(B, ts_scl(-2.0 * (2.0 - nu) / c2, rdot));
+    }
+    if (terms & 2) {
+        const double c4 = c * c * c * c;
+        const double nu2 = nu * nu;
+        const tser rd2 = ts_mul(rdot, rdot);
+        const tser rd3 = ts_mul(rd2, rdot);
+        const tser rd4 = ts_mul(rd2, rd2);
+        const tser v4 = ts_mul(v2, v2);
+        const tser rd2v2 = ts_mul(rd2, v2);
+        const tser rdv2 = ts_mul(rdot, v2);
+        tser a2 = ts_scl(15.0 / 8.0 * nu, rd4);
+        a2 = ts_add(a2, ts_scl(-45.0 / 8.0 * nu2, rd4));
+        a2 = ts_add(a2, ts_scl(-9.0 / 2.0 * nu, rd2v2));
+        a2 = ts_add(a2, ts_scl(6.0 * nu2, rd2v2));
+        a2 = ts_add(a2, ts_scl(3.0 * nu, v4));
+        a2 = ts_add(a2, ts_scl(-4.0 * nu2, v4));
+        tser a2m = ts_scl(-2.0, rd2);
+        a2m = ts_add(a2m, ts_scl(-25.0 * nu, rd2));
+        a2m = ts_add(a2m, ts_scl(-2.0 * nu2, rd2));
+        a2m = ts_add(a2m, ts_scl(-13.0 / 2.0 * nu, v2));
+        a2m = ts_add(a2m, ts_scl(2.0 * nu2, v2));
+        a2 = ts_add(a2, ts_mul(Mr, a2m));
+        a2 = ts_add(a2, ts_scl(9.0 + 87.0 / 4.0 * nu, ts_mul(Mr, Mr)));
+        tser b2 = ts_scl(9.0 / 2.0 * nu, rd3);
+        b2 = ts_add(b2, ts_scl(3.0 * nu2, rd3));
+        b2 = ts_add(b2, ts_scl(-15.0 / 2.0 * nu, rdv2));
+        b2 = ts_add(b2, ts_scl(-2.0 * nu2, rdv2));
+        b2 = ts_add(b2, ts_scl(2.0 + 41.0 / 2.0 * nu + 4.0 * nu2, ts_mul(Mr, rdot)));
+        A = ts_add(A, ts_scl(1.0 / c4, a2));
+        B = ts_add(B, ts_scl(1.0 / c4, b2));
     }
     if (terms & 4) {
         const double c5 = c * c * c * c * c;

@@ -95,7 +95,7 @@ class OracleConfig:
     k_max: int = 20
     dt_rule: int = 1    # orders 6, 8: 1 = generalised criterion of the order, 2 = its order-4 form
     c_light: float = 0.0  # > 0: post-Newtonian terms between hard particles
-    pn_terms: int = 0     # 1 = 1PN, 4 = 2.5PN, 5 = both
+    pn_terms: int = 0     # a sum of 1 = 1PN, 2 = 2PN, 4 = 2.5PN
 
     def _c(self) -> _Config:
         return _Config(self.order, self.eps2, self.n_hard, self.eta, self.eta_start, self.k_min, self.k_max,
@@ -203,8 +203,8 @@ def force_nb(cfg: OracleConfig, m, x, v, act, h2, max_nb: int):
 
 def pn_rel(M: float, nu: float, c: float, terms: int, x, v):
     """Post-Newtonian part of the two-body relative acceleration (1PN: terms
-    & 1, 2.5PN: terms & 4) at relative position x and velocity v, and its time
-    derivative along the Newtonian two-body motion."""
+    & 1, 2PN: terms & 2, 2.5PN: terms & 4) at relative position x and
+    velocity v, and its time derivative along the Newtonian two-body motion."""
     lib = _load()
     x = _f64(x, (3,))
     v = _f64(v, (3,))

@@ -10,6 +10,12 @@ two-body terms in harmonic coordinates) against results the physics fixes:
 * 1PN: the circular-orbit frequency omega^2 = (M/r^3)(1 - (3 - nu) M/(c^2 r)),
   and the periastron advance per orbit 6 pi M / (c^2 a (1 - e^2)) from
   Gauss' perturbation equation integrated over a Kepler orbit;
+* 2PN: the circular-orbit frequency to second order,
+  omega^2 = (M/r^3)(1 + (nu - 3) g + (6 + 41/4 nu + nu^2) g^2), g = M/(c^2 r)
+  (its residual falls as g^3), and the conservation of the 2PN two-body
+  energy along orbits of the 1PN + 2PN equations of motion to O(c^-6) (its
+  variation falls 64-fold when c doubles; any wrong 2PN coefficient leaves a
+  c^-4 variation);
 * the jerk, snap and crackle are the time derivatives of the acceleration
   along the two-body motion (central differences of the oracle's own
   acceleration on the integrated two-body path);
@@ -92,6 +98,139 @@ def test_1pn_circular_frequency(nu):
     assert abs(a[1]) < 1e-18
 
 
+def _circular_omega2(M, nu, c, r, terms):
+    """omega^2 of the circular orbit of radius r under Newton + the oracle's
+    PN terms: v^2 = r |a(v)| solved by fixed-point iteration (rdot = 0, so
+    only the radial A term acts)."""
+    v2 = M / r
+    for _ in range(60):
+        a, _ = oracle.pn_rel(M, nu, c, terms, [r, 0.0, 0.0], [0.0, np.sqrt(v2), 0.0])
+        v2_new = r * (M / r ** 2 - a[0])
+        if v2_new == v2:
+            break
+        v2 = v2_new
+    return v2 / r ** 2
+
+
+@pytest.mark.parametrize("nu", [0.25, 0.21, 0.0])
+def test_2pn_circular_frequency(nu):
+    """The circular-orbit frequency with the 1PN and 2PN terms matches the
+    2PN series omega^2 = (M/r^3)(1 + (nu - 3) g + (6 + 41/4 nu + nu^2) g^2),
+    g = M/(c^2 r), up to a residual of order g^3 (it falls ~64-fold when c
+    doubles); with the 1PN terms alone the residual is of order g^2."""
+    M, r = 1.0, 10.0
+    res = {}
+    for c in (10.0, 20.0):
+        g = M / (c * c * r)
+        series = M / r ** 3 * (1 + (nu - 3) * g + (6 + 41 / 4 * nu + nu * nu) * g * g)
+        res[c] = _circular_omega2(M, nu, c, r, 3) / series - 1.0
+        res[c, 1] = _circular_omega2(M, nu, c, r, 1) / series - 1.0
+        assert abs(res[c]) <= 100 * g ** 3
+    assert 40 < abs(res[10.0] / res[20.0]) < 100
+    assert 12 < abs(res[10.0, 1] / res[20.0, 1]) < 20
+
+
+def _energy_2pn(M, nu, c, x, v):
+    """Conserved energy per reduced mass of the 2PN two-body motion in
+    harmonic coordinates (Blanchet 2014, Living Rev. Relativ. 17, 2): the
+    Newtonian, 1PN and 2PN truncations.  Plain arithmetic and one square
+    root, so that it also takes complex arguments (complex-step gradients)."""
+    r = np.sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+    v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2]
+    rd = (x[0] * v[0] + x[1] * v[1] + x[2] * v[2]) / r
+    Mr = M / r
+    e0 = v2 / 2 - Mr
+    e1 = 3 / 8 * v2 ** 2 - 9 / 8 * nu * v2 ** 2 + Mr * (rd ** 2 * nu / 2 + 3 / 2 * v2 + nu * v2 / 2) + Mr ** 2 / 2
+    e2 = (5 / 16 * v2 ** 3 - 35 / 16 * nu * v2 ** 3 + 65 / 16 * nu ** 2 * v2 ** 3
+          + Mr * (-3 / 8 * rd ** 4 * nu + 9 / 8 * rd ** 4 * nu ** 2 + 1 / 4 * rd ** 2 * nu * v2
+                  - 15 / 4 * rd ** 2 * nu ** 2 * v2 + 21 / 8 * v2 ** 2 - 23 / 8 * nu * v2 ** 2
+                  - 27 / 8 * nu ** 2 * v2 ** 2)
+          + Mr ** 2 * (rd ** 2 / 2 + 69 / 8 * rd ** 2 * nu + 3 / 2 * rd ** 2 * nu ** 2 + 7 / 4 * v2
+                       - 55 / 8 * nu * v2 + nu ** 2 * v2 / 2)
+          + Mr ** 3 * (-1 / 2 - 15 / 4 * nu))
+    return e0, e0 + e1 / c ** 2, e0 + e1 / c ** 2 + e2 / c ** 4
+
+
+def _energy_variation(M, nu, c, e, steps=16000, orbits=1.5):
+    """Largest change of the 1PN and 2PN energies along the 1PN + 2PN
+    relative equation of motion (Newton + oracle PN terms) from the
+    pericentre of a Kepler orbit of eccentricity e, a = 1: RK4 in the
+    Sundman variable s (dt = r ds, so that the steps shrink with r at
+    pericentre)."""
+    y = np.array([1.0 - e, 0.0, 0.0, 0.0, np.sqrt(M * (1 + e) / (1 - e)), 0.0])
+    h = orbits * 2 * np.pi / steps   # ds; one orbit spans about 2 pi in s (a = 1)
+
+    def f(y):
+        x, v = y[:3], y[3:]
+        r = np.linalg.norm(x)
+        pn, _ = oracle.pn_rel(M, nu, c, 3, x, v)
+        return r * np.concatenate([v, -M * x / r ** 3 + pn])
+
+    e1, e2 = [], []
+    for _ in range(steps):
+        k1 = f(y); k2 = f(y + h / 2 * k1); k3 = f(y + h / 2 * k2); k4 = f(y + h * k3)
+        y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        _, a1, a2 = _energy_2pn(M, nu, c, y[:3], y[3:])
+        e1.append(a1)
+        e2.append(a2)
+    return np.ptp(e1), np.ptp(e2)
+
+
+def _energy_rate(M, nu, c, x, v):
+    """dE_2PN/dt = grad_x E . v + grad_v E . a at one phase-space point, with
+    a = Newton + the oracle's 1PN + 2PN terms; the gradient by complex steps
+    (exact to rounding)."""
+    pn, _ = oracle.pn_rel(M, nu, c, 3, x, v)
+    a = -M * x / np.linalg.norm(x) ** 3 + pn
+    rate = 0.0
+    for k in range(3):
+        dx = np.zeros(3, complex)
+        dx[k] = 1e-30j
+        rate += _energy_2pn(M, nu, c, x + dx, v.astype(complex))[2].imag / 1e-30 * v[k]
+        rate += _energy_2pn(M, nu, c, x.astype(complex), v + dx)[2].imag / 1e-30 * a[k]
+    return rate
+
+
+def test_2pn_energy_rate_is_order_c6():
+    """At phase-space points (the identity holds at any point, bound or not)
+    the rate of change of the 2PN energy under the 1PN + 2PN equations of
+    motion is O(c^-6): doubling c shrinks it ~64-fold at every point.  A
+    wrong 2PN coefficient of the acceleration leaves an O(c^-4) rate
+    (16-fold).  Two sets: random directions with |v|^2 ~ M/r, and nearly
+    radial motion at up to three times that speed, where the terms in powers
+    of rdot weigh most."""
+    rng = np.random.default_rng(35)
+    M = 1.0
+    for radial in (False, True):
+        ratios = []
+        for _ in range(16):
+            nu = rng.uniform(0.15, 0.25)
+            x = rng.normal(size=3)
+            x *= rng.uniform(0.5, 2.0) / np.linalg.norm(x)
+            v = rng.normal(size=3) + (8.0 * x / np.linalg.norm(x) if radial else 0.0)
+            v *= rng.uniform(0.5, 3.0 if radial else 1.5) * np.sqrt(M / np.linalg.norm(x)) / np.linalg.norm(v)
+            r1, r2 = (_energy_rate(M, nu, c, x, v) for c in (80.0, 160.0))
+            ratios.append(r1 / r2)
+        assert np.all((np.array(ratios) > 55) & (np.array(ratios) < 75)), ratios
+
+
+@pytest.mark.parametrize("e", [0.5, 0.85])
+def test_2pn_energy_conserved_to_order_c6(e):
+    """Along orbits of the 1PN + 2PN equations of motion (nu = 1/4, where
+    the nu^2 terms weigh most; e = 0.85 makes the rdot^4 terms count) the 2PN
+    energy changes only at O(c^-6): doubling c shrinks its variation ~64-fold,
+    while the 1PN energy's variation (O(c^-4), the 2PN terms being on)
+    shrinks ~16-fold."""
+    M, nu = 1.0, 0.25
+    c0 = 10.0 if e < 0.7 else 24.0
+    d1 = _energy_variation(M, nu, c0, e)
+    d2 = _energy_variation(M, nu, 2 * c0, e)
+    r1, r2 = d1[0] / d2[0], d1[1] / d2[1]
+    assert 12 < r1 < 20, r1
+    assert 45 < r2 < 90, r2
+    assert d1[1] < 0.05 * d1[0]
+
+
 @pytest.mark.parametrize("e", [0.2, 0.6])
 def test_1pn_periastron_advance(e):
     """Gauss' equation for the argument of periastron, planar orbit:
@@ -122,10 +261,10 @@ def test_jerk_is_time_derivative_along_two_body_motion():
         x = rng.normal(size=3)
         v = rng.normal(size=3) * np.sqrt(M / np.linalg.norm(x))
         an = -M * x / np.linalg.norm(x) ** 3
-        _, j = oracle.pn_rel(M, nu, c, 5, x, v)
+        _, j = oracle.pn_rel(M, nu, c, 7, x, v)
         h = 1e-4
-        ap, _ = oracle.pn_rel(M, nu, c, 5, x + v * h + an * h * h / 2, v + an * h)
-        am, _ = oracle.pn_rel(M, nu, c, 5, x - v * h + an * h * h / 2, v - an * h)
+        ap, _ = oracle.pn_rel(M, nu, c, 7, x + v * h + an * h * h / 2, v + an * h)
+        am, _ = oracle.pn_rel(M, nu, c, 7, x - v * h + an * h * h / 2, v - an * h)
         fd = (ap - am) / (2 * h)
         np.testing.assert_allclose(j, fd, rtol=1e-6, atol=1e-9 * np.abs(j).max())
 
@@ -156,12 +295,12 @@ def test_snap_and_crackle_are_time_derivatives_along_two_body_motion():
         M, nu, c = rng.uniform(0.5, 2.0), rng.uniform(0.05, 0.25), rng.uniform(5.0, 20.0)
         x = rng.normal(size=3)
         v = rng.normal(size=3) * np.sqrt(M / np.linalg.norm(x))
-        d = oracle.pn_rel_derivs(M, nu, c, 5, x, v)
-        a, j = oracle.pn_rel(M, nu, c, 5, x, v)
+        d = oracle.pn_rel_derivs(M, nu, c, 7, x, v)
+        a, j = oracle.pn_rel(M, nu, c, 7, x, v)
         np.testing.assert_array_equal(d[0], a)
         np.testing.assert_array_equal(d[1], j)
         h = 2e-3
-        f = {k: oracle.pn_rel(M, nu, c, 5, xs, vs)[0]
+        f = {k: oracle.pn_rel(M, nu, c, 7, xs, vs)[0]
              for k, (xs, vs) in zip((-2, -1, 1, 2), _two_body_path(M, x, v, (-2 * h, -h, h, 2 * h)))}
         f[0] = a
         snap = (f[1] - 2 * f[0] + f[-1]) / h ** 2
