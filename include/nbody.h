@@ -83,7 +83,7 @@ typedef struct {
     double c_light;     /* speed of light in the model's units (G = 1); > 0 with pn_terms != 0
                            adds post-Newtonian terms between the hard particles (the paper's
                            relativistic corrections for black-hole binaries, Introduction): for
-                           every pair of particles with indices < n_hard, the 1PN and / or
+                           every pair of particles with indices < n_hard, the 1PN, 2PN and / or
                            2.5PN two-body relative acceleration in harmonic coordinates,
                            -(M/r^2)[A n + B v] with the A, B terms of Blanchet's review
                            (Living Rev. Relativ. 17, 2), body 1 taking m2/M of it and body 2
@@ -93,7 +93,7 @@ typedef struct {
                            from their positions and velocities predicted in FP64.
                            n_hard <= 1024 (the pairs cost n_hard^2); not in the batched form
                            (NBODY_E_UNSUPPORTED).  0 = off. */
-    int32_t pn_terms;   /* 1 = 1PN, 4 = 2.5PN (radiation reaction), 5 = both; 0 = off */
+    int32_t pn_terms;   /* a sum of 1 = 1PN, 2 = 2PN, 4 = 2.5PN (radiation reaction); 0 = off */
 } nbody_config;
 
 /* Particle state, DEVICE pointers, caller-owned, 8-byte aligned.

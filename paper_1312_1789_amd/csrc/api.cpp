@@ -33,8 +33,9 @@ nbody_status check_config(const nbody_config *c)
     if (c->k_min < 0 || c->k_min > c->k_max || c->k_max > nb::kLevelMax)
         return fail(NBODY_E_INVALID, "need 0 <= k_min <= k_max <= 20 (got %d, %d)", c->k_min, c->k_max);
     if (!(c->c_light >= 0.0) || !std::isfinite(c->c_light)) return fail(NBODY_E_INVALID, "c_light must be finite and >= 0");
-    if (c->pn_terms != 0 && c->pn_terms != 1 && c->pn_terms != 4 && c->pn_terms != 5)
-        return fail(NBODY_E_INVALID, "pn_terms must be 0, 1, 4 or 5 (got %d)", c->pn_terms);
+    if (c->pn_terms < 0 || c->pn_terms > 7)
+        return fail(NBODY_E_INVALID, "pn_terms must be a sum of 1 (1PN), 2 (2PN) and 4 (2.5PN) (got %d)",
+                    c->pn_terms);
     if (nb::pn_on(*c) && c->n_hard > 1024)
         return fail(NBODY_E_INVALID, "post-Newtonian terms take at most 1024 hard particles (got %lld)",
                     (long long)c->n_hard);

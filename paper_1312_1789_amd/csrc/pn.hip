@@ -8,6 +8,11 @@
 // -(M / r^2) [A n + B v] with (Blanchet, Living Rev. Relativ. 17, 2)
 //   1PN:   A = (-3/2 nu rdot^2 + (1 + 3 nu) v^2 - 2 (2 + nu) M/r) / c^2,
 //          B = -2 (2 - nu) rdot / c^2,
+//   2PN:   A = (15/8 nu rdot^4 - 45/8 nu^2 rdot^4 - 9/2 nu rdot^2 v^2 + 6 nu^2 rdot^2 v^2
+//               + 3 nu v^4 - 4 nu^2 v^4 + (M/r)(-2 rdot^2 - 25 nu rdot^2 - 2 nu^2 rdot^2
+//               - 13/2 nu v^2 + 2 nu^2 v^2) + (M/r)^2 (9 + 87/4 nu)) / c^4,
+//          B = (9/2 nu rdot^3 + 3 nu^2 rdot^3 - 15/2 nu rdot v^2 - 2 nu^2 rdot v^2
+//               + (M/r)(2 + 41/2 nu + 4 nu^2) rdot) / c^4,
 //   2.5PN: A = -8/5 nu (M/r) rdot (17/3 M/r + 3 v^2) / c^5,
 //          B =  8/5 nu (M/r) (3 M/r + v^2) / c^5.
 // Body 1 takes m2 / M of it, body 2 minus m1 / M.  Jerk, snap and crackle
@@ -124,6 +129,21 @@ __device__ void pn_relative(double M, double nu, double c, int terms, const doub
         const double ic2 = 1.0 / (c * c);
         A = A + ic2 * ((-1.5 * nu) * (rdot * rdot) + (1.0 + 3.0 * nu) * v2 + (-2.0 * (2.0 + nu)) * Mr);
         B = B + (-2.0 * (2.0 - nu) * ic2) * rdot;
+    }
+    if (terms & 2) {
+        // grouped by powers of rdot and v^2; the same terms as the 2PN A, B
+        const double ic4 = 1.0 / (c * c * c * c);
+        const double nu2 = nu * nu;
+        const TS rd2 = rdot * rdot;
+        const TS rm = Mr * rdot;
+        const TS a2 = rd2 * ((15.0 / 8.0 * nu - 45.0 / 8.0 * nu2) * rd2 + (6.0 * nu2 - 4.5 * nu) * v2) +
+                      (3.0 * nu - 4.0 * nu2) * (v2 * v2) +
+                      Mr * ((-2.0 - 25.0 * nu - 2.0 * nu2) * rd2 + (2.0 * nu2 - 6.5 * nu) * v2 +
+                            (9.0 + 87.0 / 4.0 * nu) * Mr);
+        const TS b2 = rdot * ((4.5 * nu + 3.0 * nu2) * rd2 + (-7.5 * nu - 2.0 * nu2) * v2) +
+                      (2.0 + 20.5 * nu + 4.0 * nu2) * rm;
+        A = A + ic4 * a2;
+        B = B + ic4 * b2;
     }
     if (terms & 4) {
         const double ic5 = 1.0 / (c * c * c * c * c);

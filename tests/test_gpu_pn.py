@@ -13,6 +13,7 @@ the physics the oracle pins fix:
   FP64 run ends where the oracle's integration ends;
 * an eccentric two-body orbit with the 1PN terms advances its periastron by
   6 pi M / (c^2 a (1 - e^2)) per orbit.
+The 2PN terms (pn_terms & 2) take part in the init and step parity cases.
 """
 import numpy as np
 import pytest
@@ -52,11 +53,14 @@ def _bh_model(n_bh):
     return model
 
 
-@pytest.mark.parametrize("order,precision,n_bh", [(4, "fp64", 2), (4, "mixed", 2), (6, "fp64", 2), (8, "fp64", 2),
-                                                  (8, "mixed", 2), (4, "fp64", 3), (6, "fp64", 3)])
-def test_pn_init_and_step_parity(order, precision, n_bh):
+# pn_terms: 5 = 1PN + 2.5PN, 7 = 1PN + 2PN + 2.5PN, 2 = 2PN alone
+@pytest.mark.parametrize("order,precision,n_bh,terms", [(4, "fp64", 2, 5), (4, "mixed", 2, 5), (6, "fp64", 2, 5),
+                                                        (8, "fp64", 2, 5), (8, "mixed", 2, 5), (4, "fp64", 3, 5),
+                                                        (6, "fp64", 3, 5), (4, "fp64", 2, 7), (6, "mixed", 2, 7),
+                                                        (8, "fp64", 2, 7), (8, "fp64", 3, 2)])
+def test_pn_init_and_step_parity(order, precision, n_bh, terms):
     model = _bh_model(n_bh)
-    sim = _sim(model.m, model.x, model.v, precision, 2.0, 5, n_hard=n_bh, order=order,
+    sim = _sim(model.m, model.x, model.v, precision, 2.0, terms, n_hard=n_bh, order=order,
                eta=0.01 if order == 4 else 0.1)
     ocfg = _ocfg(sim)
     sim.init()
