@@ -232,9 +232,7 @@ def batched_clusters(n_clusters: int, seed: int = 1400):
     """Cluster sizes round(2^U(10, 16)) from one seeded draw; cluster c is a
     Plummer model with seed seed + c."""
     import nbody_ics
-    rng = np.random.Generator(np.random.PCG64(seed))
-    sizes = np.round(2.0 ** rng.uniform(10.0, 16.0, n_clusters)).astype(int)
-    return [nbody_ics.plummer(int(s), seed + c) for c, s in enumerate(sizes)]
+    return nbody_ics.batched_plummer(n_clusters, seed)
 
 
 def run_batched(args):
@@ -298,6 +296,7 @@ def run_batched(args):
                "interactions": inter, "mean_active_per_batched_step": nact,
                "launch": {"force_grid": shape[0], "items_per_wg": shape[1], "i_tile": shape[2]},
                "cluster_time_range": [min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20]}
+    h_graph = B.to_numpy()
     del B
     # the same steps launched eagerly (no graph)
     E = Batch(clusters, precision="mixed", **kw)
@@ -313,11 +312,19 @@ def run_batched(args):
     e1 = E.stats()
     log("[batched eager] %.3f ms/step, %.4e interactions/s" % (ewall / args.steps * 1e3,
                                                               (e1.interactions - e0.interactions) / ewall))
+    h_eager = E.to_numpy()
+    same = all(np.array_equal(h_graph[k], h_eager[k]) for k in ("x", "v", "t_tick", "level")) and \
+        all(np.array_equal(a, b) for a, b in zip(h_graph["d"], h_eager["d"]))
+    log("[batched eager] final state %s the graph replays' bit for bit" % ("equals" if same else "DIFFERS FROM"))
     eager = {"interactions_per_s": (e1.interactions - e0.interactions) / ewall,
-             "ms_per_batched_step": ewall / args.steps * 1e3}
+             "ms_per_batched_step": ewall / args.steps * 1e3, "final_state_equals_graph": bool(same)}
     del E
     # one context per cluster, the same number of block steps each, same start
     tot_inter, tot_wall, tot_steps = 0.0, 1e-30, 0
+    # clusters whose final state is compared with the batched run's (the
+    # single-system force kernels sum in another order: not bit for bit)
+    check = set(np.argsort(sizes)[[0, len(sizes) // 2, len(sizes) - 1]].tolist())
+    state_diff = {}
     for c, m in enumerate([] if args.skip_per_cluster else models):
         sim = Simulation(m.m, m.x, m.v, precision="mixed", **kw)
         a, b = sum(sizes[:c]), sum(sizes[:c + 1])
@@ -334,6 +341,13 @@ def run_batched(args):
         tot_wall += time.perf_counter() - t0
         tot_inter += sim.stats().interactions - a0
         tot_steps += args.steps
+        if c in check:
+            hc = sim.to_numpy()
+            same_t = bool(np.array_equal(hc["t_tick"], h_graph["t_tick"][a:b]))
+            dx = float(np.max(np.abs(hc["x"] - h_graph["x"][:, a:b])))
+            state_diff[int(c)] = {"n": int(m.n), "times_equal": same_t, "max_abs_dx": dx}
+            log("[per-cluster] cluster %d (n %d) vs batched: times %s, max |dx| %.2e"
+                % (c, m.n, "equal" if same_t else "DIFFER", dx))
         if c % 32 == 31:
             log("[per-cluster] %d clusters done, %.1f s timed" % (c + 1, tot_wall))
         sim.close()
@@ -341,7 +355,7 @@ def run_batched(args):
     log("[per-cluster] %d steps over %d contexts: %.1f s, %.4e interactions/s"
         % (tot_steps, len(models), tot_wall, tot_inter / tot_wall))
     per_cluster = {"interactions_per_s": tot_inter / tot_wall, "seconds": tot_wall, "interactions": tot_inter,
-                   "skipped": bool(args.skip_per_cluster)}
+                   "skipped": bool(args.skip_per_cluster), "final_state_vs_batched": state_diff}
     line = {
         "metric": BATCH_METRIC,
         "value": batched["interactions_per_s"],
@@ -606,26 +620,8 @@ def run_neighbour(args):
 
 
 def binary_gw(h, c, i=0, j=1):
-    """Diagnostics of the pair (i, j) from a to_numpy() state: Newtonian
-    relative-orbit semi-major axis a and eccentricity e, Peters' (1964)
-    orbit-averaged gravitational-wave luminosity (32/5) nu^2 M^5 / (a^5 c^5)
-    (1 + 73/24 e^2 + 37/96 e^4) / (1 - e^2)^(7/2) and his circular-orbit
-    inspiral time (5/256) a^4 c^5 / (nu M^3) (G = 1)."""
-    m1, m2 = h["m"][i], h["m"][j]
-    M = m1 + m2
-    nu = m1 * m2 / (M * M)
-    r = h["x"][:, i] - h["x"][:, j]
-    w = h["v"][:, i] - h["v"][:, j]
-    rn = np.linalg.norm(r)
-    a = -M / (2.0 * (0.5 * np.dot(w, w) - M / rn))
-    ecc = np.linalg.norm(np.cross(w, np.cross(r, w)) / M - r / rn)
-    e2 = ecc * ecc
-    out = {"a": float(a), "e": float(ecc)}
-    if c > 0 and a > 0 and e2 < 1:
-        out["gw_luminosity"] = float(32.0 / 5.0 * nu ** 2 * M ** 5 / (a ** 5 * c ** 5)
-                                     * (1 + 73.0 / 24.0 * e2 + 37.0 / 96.0 * e2 * e2) / (1 - e2) ** 3.5)
-        out["inspiral_time_circular"] = float(5.0 / 256.0 * a ** 4 * c ** 5 / (nu * M ** 3))
-    return out
+    from paper_1312_1789_amd.diagnostics import binary_gw as _gw
+    return _gw(h, c, i, j)
 
 
 def run_pn(args):
@@ -647,7 +643,7 @@ def run_pn(args):
         return -M / (2.0 * (0.5 * np.dot(w, w) - M / r))
 
     runs = {}
-    for label, c, terms in (("newtonian", 0.0, 0), ("pn_1_2.5", args.pn_c, 5)):
+    for label, c, terms in (("newtonian", 0.0, 0), ("pn_1_2_2.5", args.pn_c, 7)):
         sim = Simulation(model.m, model.x, model.v, order=4, precision="mixed", eps2=1e-8, n_hard=2, eta=0.01,
                          eta_start=0.01, c_light=c, pn_terms=terms)
         sim.init()
@@ -687,12 +683,12 @@ def run_pn(args):
     log("[pn] two-body inspiral (c = 8, 2.5PN): da/dt %.5e, Peters %.5e (ratio %.4f)" % (rate, peters, rate / peters))
     sim.close()
     line = {"metric": "whole-step interactions/s with post-Newtonian black-hole terms (4th order, MIXED)",
-            "value": runs["pn_1_2.5"]["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1,
+            "value": runs["pn_1_2_2.5"]["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1,
             "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
             "config": {"workload": "King W0=7 %d stars + BH binary (0.01 + 0.01 at separation 0.2), c = %g, "
                                    "t = 0 -> %.5f" % (n_stars, args.pn_c, t_end / 2.0 ** 20)},
             "runs": runs, "pn_over_newtonian_time_per_step":
-                runs["pn_1_2.5"]["ms_per_step"] / runs["newtonian"]["ms_per_step"],
+                runs["pn_1_2_2.5"]["ms_per_step"] / runs["newtonian"]["ms_per_step"],
             "two_body_inspiral": {"da_dt": rate, "peters": peters}}
     print(json.dumps(line), flush=True)
 
@@ -837,7 +833,7 @@ def run_c3(args):
     torch.cuda.empty_cache()
     if args.c3_c > 0:
         sim, relat = integrate_run(model, "c3, post-Newtonian", t_end, hist_pass=False, c_light=args.c3_c,
-                                   pn_terms=5, **kw)
+                                   pn_terms=7, **kw)
         sim.close()
         del sim
         torch.cuda.empty_cache()
@@ -872,7 +868,7 @@ def main():
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
     ap.add_argument("--c3-t-end", type=float, default=1.0 / 256)
-    ap.add_argument("--c3-c", type=float, default=0.0, help="c3: also run with 1PN + 2.5PN terms at this c")
+    ap.add_argument("--c3-c", type=float, default=0.0, help="c3: also run with 1PN + 2PN + 2.5PN terms at this c")
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")
     ap.add_argument("--small-n", default="131072,1048576", help="smallstep: particle counts")

@@ -205,6 +205,15 @@ def active_subset(n: int, n_act: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(n, size=n_act, replace=False)).astype(np.int32)
 
 
+def batched_plummer(n_clusters: int = 256, seed: int = 1400) -> list:
+    """Independent Plummer clusters for the batched workload: sizes
+    round(2^U(10, 16)) from one seeded draw, cluster c drawn with seed
+    seed + c."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.round(2.0 ** rng.uniform(10.0, 16.0, n_clusters)).astype(int)
+    return [plummer(int(s), seed + c) for c, s in enumerate(sizes)]
+
+
 def kepler_pair(e: float = 0.5, a: float = 1.0, m1: float = 0.5, m2: float = 0.5) -> Model:
     """Two bodies at the pericentre of a Kepler orbit of eccentricity e and
     semi-major axis a (G = 1), in the centre-of-mass frame."""

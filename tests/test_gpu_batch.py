@@ -300,3 +300,58 @@ def test_batch_autotune_keeps_parity():
         st = err_stats(np.concatenate(errs[key]))
         say("after autotune %s rms %.2e max %.2e" % (key, st["rms"], st["max"]))
         assert st["max"] <= 50 * LOW_TOL[key]
+
+
+def test_batch_c4_scale():
+    """The batched workload at its configured scale: 256 Plummer clusters,
+    N_c = round(2^U(10, 16)) (seed 1400, n = 4.25M), 6th order, MIXED, one
+    batched step per captured-graph replay.  First step from the initial
+    state: every cluster's next time and active set exactly.  Second, every
+    particle on the largest step, so that the step evaluates sum N_c^2 ~
+    1.3e11 pair interactions (the plan's item cap and its partial-sum bound
+    are reached).  Forces of sampled active rows of the largest, the median
+    and the smallest cluster against the oracle, in both steps."""
+    models = nbody_ics.batched_plummer(256, 1400)
+    sizes = np.array([m.n for m in models])
+    say("C4 scale: %d clusters, n %d (min %d, max %d)" % (len(models), sizes.sum(), sizes.min(), sizes.max()))
+    B = _batch(models, 6, "mixed", n_hard=0)
+    B.init()
+    ocfg = _ocfg(B)
+    order_ = np.argsort(sizes, kind="stable")
+    picks = [int(order_[-1]), int(order_[len(order_) // 2]), int(order_[0])]
+    h_init = B.to_numpy()
+    for label in ("initial levels", "all active"):
+        if label == "all active":
+            h = dict(h_init)
+            h["level"] = np.full(B.n, 3, np.int32)
+            B.load_state(h)
+        h0 = B.to_numpy()
+        B.capture()
+        B.replay(1)
+        B.synchronize()
+        aoff, act, f = B.last_step()
+        act = act.cpu().numpy()
+        f = f.cpu().numpy()
+        say("C4 step (%s): %d active rows in all" % (label, aoff[-1]))
+        for c in range(B.nc):
+            _, want = _next(B.cluster(h0, c))
+            np.testing.assert_array_equal(act[aoff[c]:aoff[c + 1]] - B.off[c], want)
+        if label == "all active":
+            assert aoff[-1] == B.n
+        errs = {k: [] for k in KEYS[:3]}
+        for c in picks:
+            hc = B.cluster(h0, c)
+            T, want = _next(hc)
+            rows = np.arange(want.size) if want.size <= 64 else \
+                np.sort(np.random.default_rng(c).choice(want.size, 64, replace=False))
+            os0 = _ostate(hc, 6)
+            xp, vp, ap, _ = oracle.predict(ocfg, os0, T)
+            F = oracle.force(ocfg, os0.m, xp, vp, ap, None, act=want[rows], with_pot=False)
+            for k, key in enumerate(KEYS[:3]):
+                errs[key].append(rel_err(f[k][:, aoff[c] + rows], F[key]))
+            say("  cluster %d (N_c %d): %d active, %d checked" % (c, sizes[c], want.size, rows.size))
+        for key in KEYS[:3]:
+            st = err_stats(np.concatenate(errs[key]))
+            say("  C4 %s %s rms %.2e max %.2e" % (label, key, st["rms"], st["max"]))
+            assert st["rms"] <= LOW_TOL[key] and st["max"] <= 10 * LOW_TOL[key], (key, st)
+    B.close()

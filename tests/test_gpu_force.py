@@ -9,7 +9,12 @@ Tolerances:
 * MIXED and DS: rms relative error <= 2e-6 (acceleration) and <= 2e-5 (jerk),
   the accuracy bar of the mixed-precision scheme; snap and crackle,
   higher derivatives with more cancellation, rms <= 2e-4 / 2e-3; potential
-  rms <= 1e-6.
+  rms <= 1e-6.  The largest error of any row is bounded at ten times those
+  values: FP32 terms carry a relative error of a few 2^-24 each, and a row's
+  error relative to its sum grows with how much its terms cancel
+  (sum |t_j| / |sum t_j|), which is several times the typical value on the
+  rare rows whose jerk, snap or crackle nearly vanish (measured: every
+  row's error below 0.4 times the rms bar).
 """
 import numpy as np
 import pytest
@@ -22,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = {"rms": 1e-12, "max": 1e-9}
 LOW_TOL = {"acc": 2e-6, "jrk": 2e-5, "snp": 2e-4, "crk": 2e-3, "pot": 1e-6}
+LOW_MAX = {k: 10.0 * v for k, v in LOW_TOL.items()}
 KEYS = {4: ["acc", "jrk"], 6: ["acc", "jrk", "snp"], 8: ["acc", "jrk", "snp", "crk"]}
 
 
@@ -43,7 +49,7 @@ def _check(out, ref, order, precision, act_n):
         if precision == "fp64":
             assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (key, st)
         else:
-            assert st["rms"] <= LOW_TOL[key], (key, st)
+            assert st["rms"] <= LOW_TOL[key] and st["max"] <= LOW_MAX[key], (key, st)
 
 
 @pytest.fixture(scope="module")
@@ -189,24 +195,103 @@ def test_unsoftened_pair_and_empty_call():
     sim.force_block(empty)
 
 
+# launch shapes the benchmark fixes for the all-active force at n = 2^20
+# (ni, block, n_split, jpath)
+BENCH_SHAPE = {"mixed": (2, 256, 16, 2), "fp64": (2, 128, 16, 1)}
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_force_full_size_sampled(precision):
     """The headline workload: King W0=7, n = 2^20, 6th order, all particles
-    active in one call (the launch the benchmark times); 256 sampled rows
-    are checked against the oracle."""
+    active in one call, in the untuned default launch and in the launch the
+    benchmark times (which must run as asked: 16 splits); 256 sampled rows
+    are checked against the oracle in both, and the two agree to the
+    summation-order difference."""
     n = 1 << 20
     say("full-size force %s n=%d" % (precision, n))
     model = nbody_ics.king(n, 7.0, 13)
     d = random_derivs(n, 1313, 8)
     sim = _sim(model, 6, precision, 1e-8, 0, d)
     act = torch.arange(n, dtype=torch.int32, device=sim.device)
-    out = sim.force_block(act)
-    torch.cuda.synchronize()
     sample = nbody_ics.active_subset(n, 256, 1520)
     ref = oracle_force(6, 1e-8, 0, model.m, model.x, model.v, d[0], None, act=sample)
     idx = torch.as_tensor(sample.astype(np.int64), device=sim.device)
-    got = {k: t[..., idx] for k, t in out.items()}
-    _check(got, ref, 6, precision, sample.size)
+    outs = []
+    for shape in (None, BENCH_SHAPE[precision]):
+        if shape is not None:
+            sim.set_launch(*shape)
+        out = sim.force_block(act, with_pot=False)
+        torch.cuda.synchronize()
+        used = sim.last_launch()
+        say("  launch %s ran as %s" % (shape or "default", used))
+        if shape is not None:
+            assert used == shape, (used, shape)
+        got = {k: t[..., idx] for k, t in out.items() if k != "pot"}
+        for key in KEYS[6]:
+            st = err_stats(rel_err(got[key].cpu().numpy(), ref[key]))
+            say("   %-6s %-4s rms %.2e max %.2e" % (precision, key, st["rms"], st["max"]))
+            if precision == "fp64":
+                assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (key, st)
+            else:
+                assert st["rms"] <= LOW_TOL[key] and st["max"] <= LOW_MAX[key], (key, st)
+        outs.append(out["acc"].clone())
+    diff = float(((outs[0] - outs[1]).norm(dim=0) / outs[1].norm(dim=0)).max())
+    say("  default vs benchmark launch: max relative difference %.2e" % diff)
+    assert diff <= (1e-12 if precision == "fp64" else 1e-5)
+    sim.close()
+
+
+def test_force_c3_size_sampled():
+    """The C3 system at its size and order: King W0=7 with 2^20 stars plus a
+    black-hole binary (n = 2^20 + 2, n_hard = 2: the two black holes are
+    mutually unsoftened), 8th order, MIXED, all particles active, in the
+    default launch and with 16 splits; 254 random rows plus both black holes
+    against the oracle (stored derivatives seeded, |a| ~ 1)."""
+    model = cluster_with_bh(1 << 20, 13)
+    n = model.n
+    d = random_derivs(n, 1314, 8)
+    sim = _sim(model, 8, "mixed", 1e-8, 2, d)
+    act = torch.arange(n, dtype=torch.int32, device=sim.device)
+    sample = np.concatenate([np.array([0, 1], np.int32), nbody_ics.active_subset(n - 2, 254, 1521) + 2])
+    ref = oracle_force(8, 1e-8, 2, model.m, model.x, model.v, d[0], d[1], act=sample)
+    idx = torch.as_tensor(sample.astype(np.int64), device=sim.device)
+    for shape in (None, (2, 256, 16, 2)):
+        if shape is not None:
+            sim.set_launch(*shape)
+        out = sim.force_block(act, with_pot=False)
+        torch.cuda.synchronize()
+        say("C3 force n=%d order 8 mixed, launch %s ran as %s" % (n, shape or "default", sim.last_launch()))
+        got = {k: t[..., idx].cpu().numpy() for k, t in out.items() if k != "pot"}
+        for key in KEYS[8]:
+            e = rel_err(got[key], ref[key])
+            st = err_stats(e)
+            say("   %-4s rms %.2e max %.2e; black holes %.2e %.2e" % (key, st["rms"], st["max"], e[0], e[1]))
+            assert st["rms"] <= LOW_TOL[key] and st["max"] <= LOW_MAX[key], (key, st)
+            assert max(e[0], e[1]) <= LOW_TOL[key], key
+    sim.close()
+
+
+def test_last_launch_reports_split_bounds(small_case):
+    """A requested split count is lowered to what the partial-sum scratch
+    holds (n_act * n_split <= 2^21 rows at this size) and to splits of at
+    least 128 j; nbody_get_last_launch reports what ran."""
+    model, eps2, n_hard, d = small_case
+    n = model.n
+    sim = _sim(model, 6, "mixed", eps2, n_hard, d)
+    assert sim.last_launch() == (0, 0, 0, 0)
+    act = torch.arange(n, dtype=torch.int32, device=sim.device)
+    for req in (1, 5, 23, 24, 65535):
+        sim.set_launch(2, 128, req, 2)
+        sim.force_block(act, with_pot=False)
+        sp = min(req, (1 << 21) // n)
+        chunk = -(-(-(-n // sp)) // 128) * 128
+        want = -(-n // chunk)
+        assert sim.last_launch() == (2, 128, want, 2), (req, sim.last_launch(), want)
+    sim.set_launch(2, 256, 0, 3)   # the wave j-split kernel ignores ni and block
+    sim.force_block(act[:5], with_pot=False)
+    got = sim.last_launch()
+    assert got[0] == 1 and got[1] == 64 and got[3] == 3 and got[2] >= 1
+    sim.close()
 
 
 def test_force_max_size_sampled():
@@ -278,7 +363,7 @@ def test_wave_split_kernel_parity(small_case, order, precision):
         if precision == "fp64":
             assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (key, st)
         else:
-            assert st["rms"] <= LOW_TOL[key], (key, st)
+            assert st["rms"] <= LOW_TOL[key] and st["max"] <= LOW_MAX[key], (key, st)
     # reruns are bitwise identical
     act = torch.as_tensor(sets[6], device=sim.device)
     a1 = sim.force_block(act)["acc"].cpu().numpy()

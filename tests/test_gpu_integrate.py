@@ -317,3 +317,35 @@ def test_run_reports_nonfinite():
     with pytest.raises(abi.NBodyError) as e:
         sim.run(TICKS)
     assert e.value.status == abi.NBODY_E_NONFINITE
+
+
+def test_c2_size_energy_drift_vs_oracle():
+    """C2 at its size: Plummer n = 131072 (seed 12), 6th order, eta = 0.1,
+    MIXED with its default time-step rule, t = 0 -> 1/1024 with the largest
+    step 1/1024 (k_min = 10), so that every particle is synchronised there
+    (the oracle's two initial force passes over n^2 pairs dominate its
+    time).  |dE/E| within twice the oracle's drift under the same rule (plus
+    1e-10 for the FP32 force terms); step counts within 2%; no dt
+    underflow."""
+    model = nbody_ics.plummer(131072, 12)
+    t_end = TICKS // 1024
+    sim = _sim(model, 6, precision="mixed", eta=0.1, k_min=10)
+    sim.init()
+    E0 = sum(sim.energy())
+    steps = sim.integrate(t_end)
+    E1 = sum(sim.energy())
+    dg = abs((E1 - E0) / E0)
+    got = sim.to_numpy()
+    say("C2 size, GPU MIXED (rule %d): %d steps, |dE/E| %.3e; oracle running" % (sim.dt_rule, steps, dg))
+    ocfg = _ocfg(sim)
+    os_ = oracle.State(model.m, model.x, model.v, 6)
+    oracle.init(ocfg, os_)
+    Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    st = oracle.integrate(ocfg, os_, t_end)
+    Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
+    do = abs((Eo1 - Eo0) / Eo0)
+    say("C2 size: oracle %d steps, |dE/E| %.3e" % (st["steps"], do))
+    assert np.all(got["t_tick"] == t_end)
+    assert sim.stats().dt_underflow == 0
+    assert abs(steps - st["steps"]) <= 0.02 * st["steps"]
+    assert dg <= 2.0 * do + 1e-10
