@@ -319,25 +319,34 @@ def test_run_reports_nonfinite():
     assert e.value.status == abi.NBODY_E_NONFINITE
 
 
-def test_c2_size_energy_drift_vs_oracle():
-    """C2 at its size: Plummer n = 131072 (seed 12), 6th order, eta = 0.1,
-    MIXED with its default time-step rule, t = 0 -> 1/1024 with the largest
-    step 1/1024 (k_min = 10), so that every particle is synchronised there
-    (the oracle's two initial force passes over n^2 pairs dominate its
-    time).  |dE/E| within twice the oracle's drift under the same rule (plus
-    1e-10 for the FP32 force terms); step counts within 2%; no dt
-    underflow."""
+def test_c2_size_integration_vs_oracle():
+    """C2 at its size: Plummer n = 131072 (seed 12), 6th order, eta = 0.1, the
+    order-4 form of the time-step criterion (MIXED's default), t = 0 -> 1/1024
+    with the largest step 1/1024 (k_min = 10) so that every particle is
+    synchronised there (the oracle's two initial force passes over n^2
+    pairs dominate its time).  One oracle run against the GPU in FP64 (the
+    same step count to within 1, final positions to 1e-10, |dE/E| within
+    twice the oracle's plus 1e-13) and in MIXED (step counts within 5% + 2,
+    |dE/E| within twice the oracle's plus 1e-10 for the FP32 force terms).
+    Over so short a span the drift is at the rounding level (~1e-14 to
+    1e-13): this checks integration parity at size, not the drift of a
+    whole time unit (shown against the oracle at n = 8192 over 1/8)."""
     model = nbody_ics.plummer(131072, 12)
     t_end = TICKS // 1024
-    sim = _sim(model, 6, precision="mixed", eta=0.1, k_min=10)
-    sim.init()
-    E0 = sum(sim.energy())
-    steps = sim.integrate(t_end)
-    E1 = sum(sim.energy())
-    dg = abs((E1 - E0) / E0)
-    got = sim.to_numpy()
-    say("C2 size, GPU MIXED (rule %d): %d steps, |dE/E| %.3e; oracle running" % (sim.dt_rule, steps, dg))
-    ocfg = _ocfg(sim)
+    ocfg = None
+    runs = {}
+    from paper_1312_1789_amd import Simulation
+    for prec in ("fp64", "mixed"):
+        sim = Simulation(model.m, model.x, model.v, order=6, precision=prec, eps2=1e-8, eta=0.1, eta_start=0.01,
+                         k_min=10, k_max=20, dt_rule=2)
+        sim.init()
+        E0 = sum(sim.energy())
+        steps = sim.integrate(t_end)
+        E1 = sum(sim.energy())
+        runs[prec] = (steps, abs((E1 - E0) / E0), sim.to_numpy(), sim.stats().dt_underflow)
+        say("C2 size, GPU %s (rule %d): %d steps, |dE/E| %.3e" % (prec, sim.dt_rule, steps, runs[prec][1]))
+        ocfg = _ocfg(sim)
+        sim.close()
     os_ = oracle.State(model.m, model.x, model.v, 6)
     oracle.init(ocfg, os_)
     Eo0 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
@@ -345,7 +354,14 @@ def test_c2_size_energy_drift_vs_oracle():
     Eo1 = sum(oracle.energy(ocfg, os_.m, os_.x, os_.v))
     do = abs((Eo1 - Eo0) / Eo0)
     say("C2 size: oracle %d steps, |dE/E| %.3e" % (st["steps"], do))
-    assert np.all(got["t_tick"] == t_end)
-    assert sim.stats().dt_underflow == 0
-    assert abs(steps - st["steps"]) <= 0.02 * st["steps"]
-    assert dg <= 2.0 * do + 1e-10
+    for prec, (steps, dg, got, underflow) in runs.items():
+        assert np.all(got["t_tick"] == t_end) and underflow == 0
+        if prec == "fp64":
+            assert abs(steps - st["steps"]) <= 1
+            dx = err_stats(rel_err(got["x"], os_.x))
+            say("C2 size fp64 final x vs oracle: rms %.2e max %.2e" % (dx["rms"], dx["max"]))
+            assert dx["max"] <= 1e-10
+            assert dg <= 2.0 * do + 1e-13
+        else:
+            assert abs(steps - st["steps"]) <= 0.05 * st["steps"] + 2
+            assert dg <= 2.0 * do + 1e-10
