@@ -44,6 +44,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1312_1789_amd.abi import TICK_BITS, TICKS_PER_UNIT as TICKS  # noqa: E402  (no torch import)
+
 METRIC = "pair interactions/s & % VALU peak, 6th-order N=1M, mixed vs FP64 at stated error"
 # Algorithmic flops per pair interaction: the minimal operation list of the
 # pairwise force with its potential (add/sub/mul = 1, FMA = 2, rsqrt = 1) is
@@ -187,7 +189,7 @@ def cpu_baseline_and_error(model, sims, order, target_s):
     n = model.n
     sim = sims["mixed"]
     h = sim.to_numpy()
-    T = int((h["t_tick"] + (1 << (20 - h["level"].astype(np.int64)))).min())
+    T = int((h["t_tick"] + (1 << (TICK_BITS - h["level"].astype(np.int64)))).min())
     cfg = OracleConfig(order=order, eps2=1e-8)
     st = oracle.State(h["m"], h["x"], h["v"], order, h["d"], h["t_tick"], h["level"])
     xp, vp, ap, jp = oracle.predict(cfg, st, T)
@@ -253,7 +255,7 @@ def run_batched(args):
     B.synchronize()
     log("[batched] init %.2f s" % (time.perf_counter() - t0))
     # start-up transient: every cluster to t_warm (all particles synchronised there)
-    t_warm = int(args.warm_time * 2 ** 20)
+    t_warm = int(args.warm_time * TICKS)
     B.set_end(t_warm)
     B.capture()
     t0 = time.perf_counter()
@@ -265,8 +267,8 @@ def run_batched(args):
         if live == 0:
             break
         if replays % 1024 == 0:
-            log("[batched] warm-up replay %d: %d clusters live, min time %.5f" % (replays, live, min(tcur) / 2.0 ** 20))
-    log("[batched] warm-up to t = %.4f: %d replays, %.1f s" % (t_warm / 2.0 ** 20, replays, time.perf_counter() - t0))
+            log("[batched] warm-up replay %d: %d clusters live, min time %.5f" % (replays, live, min(tcur) / TICKS))
+    log("[batched] warm-up to t = %.4f: %d replays, %.1f s" % (t_warm / TICKS, replays, time.perf_counter() - t0))
     B.set_end(1 << 62)
     tuned = None
     if args.autotune_steps > 0:
@@ -291,11 +293,11 @@ def run_batched(args):
     live, tcur = B.poll()
     log("[batched] %d graph replays: %.3f ms/replay, %.4e interactions/s, mean active %.0f per replay, "
         "cluster times %.4f..%.4f" % (args.steps, wall / args.steps * 1e3, inter / wall, nact,
-                                      min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20))
+                                      min(tcur) / TICKS, max(tcur) / TICKS))
     batched = {"interactions_per_s": inter / wall, "ms_per_batched_step": wall / args.steps * 1e3,
                "interactions": inter, "mean_active_per_batched_step": nact,
                "launch": {"force_grid": shape[0], "items_per_wg": shape[1], "i_tile": shape[2]},
-               "cluster_time_range": [min(tcur) / 2.0 ** 20, max(tcur) / 2.0 ** 20]}
+               "cluster_time_range": [min(tcur) / TICKS, max(tcur) / TICKS]}
     h_graph = B.to_numpy()
     del B
     # the same steps launched eagerly (no graph)
@@ -372,7 +374,7 @@ def run_batched(args):
         "config": {"workload": "%d Plummer clusters, N_c = round(2^U(10,16)) (seed 1400 + c), n = %d, 6th-order "
                                "Hermite block steps, MIXED force, eta = 0.1, eps = 1e-4, from t = %.4f; one batched "
                                "step = one block step of every cluster" % (len(models), sum(sizes),
-                                                                            t_warm / 2.0 ** 20),
+                                                                            t_warm / TICKS),
                    "n": sum(sizes), "clusters": len(models), "order": 6, "precision": "mixed"},
         "autotuned": tuned is not None,
         "batched_graph": batched,
@@ -423,7 +425,7 @@ def run_microbench(args):
     log("workload: King W0=6 n=%d (%.1f s to generate)" % (n, time.perf_counter() - t0))
     sizes = [k for k in (1, 16, 256, 4096, 65536) if k < n] + [n]
     orders = [int(o) for o in args.micro_orders.split(",")]
-    tick0 = 5 << 17
+    tick0 = 5 * (TICKS >> 3)
     table = []
     for order in orders:
         d = d_all[: order - 2]
@@ -518,8 +520,8 @@ def run_smallstep(args):
         model = nbody_ics.king(n, 7.0, 23)
         rng = np.random.default_rng(24)
         level = rng.integers(3, 21, n).astype(np.int32)
-        T = 3 * (1 << 17) + (1 << 15)
-        dt = 1 << (20 - level.astype(np.int64))
+        T = 3 * (TICKS >> 3) + (TICKS >> 5)
+        dt = 1 << (TICK_BITS - level.astype(np.int64))
         t_tick = (T // dt) * dt
         T = int((t_tick + dt).min())
         log("[small] King W0=7 n=%d, random block state (%.1f s to generate)" % (n, time.perf_counter() - t0))
@@ -634,7 +636,7 @@ def run_pn(args):
     from paper_1312_1789_amd import Simulation
     n_stars = args.pn_stars
     model = nbody_ics.with_bh_binary(nbody_ics.king(n_stars, 7.0, 31), 0.01, 0.2)
-    t_end = int(args.pn_t_end * 2 ** 20)
+    t_end = int(args.pn_t_end * TICKS)
 
     def binary_a(h):
         M = h["m"][0] + h["m"][1]
@@ -663,7 +665,7 @@ def run_pn(args):
                        "binary_end": binary_gw(h_end, args.pn_c)}
         log("[pn] %-9s binary at the end: %s" % (label, runs[label]["binary_end"]))
         log("[pn] %-9s %d steps to t = %.5f in %.2f s (%.3f ms/step, %.3e int/s); binary a %.6f -> %.6f"
-            % (label, steps, t_end / 2.0 ** 20, wall, runs[label]["ms_per_step"], runs[label]["interactions_per_s"],
+            % (label, steps, t_end / TICKS, wall, runs[label]["ms_per_step"], runs[label]["interactions_per_s"],
                a0, a1))
         sim.close()
         del sim
@@ -676,7 +678,7 @@ def run_pn(args):
                      c_light=8.0, pn_terms=4)
     sim.init()
     T = 16.0
-    sim.integrate(int(T * 2 ** 20))
+    sim.integrate(int(T * TICKS))
     h = sim.to_numpy()
     rate = (binary_a(h) - 1.0) / T
     peters = -64.0 / 5.0 * 0.24 / 8.0 ** 5
@@ -686,7 +688,7 @@ def run_pn(args):
             "value": runs["pn_1_2_2.5"]["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1,
             "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
             "config": {"workload": "King W0=7 %d stars + BH binary (0.01 + 0.01 at separation 0.2), c = %g, "
-                                   "t = 0 -> %.5f" % (n_stars, args.pn_c, t_end / 2.0 ** 20)},
+                                   "t = 0 -> %.5f" % (n_stars, args.pn_c, t_end / TICKS)},
             "runs": runs, "pn_over_newtonian_time_per_step":
                 runs["pn_1_2_2.5"]["ms_per_step"] / runs["newtonian"]["ms_per_step"],
             "two_body_inspiral": {"da_dt": rate, "peters": peters}}
@@ -714,11 +716,11 @@ def integrate_run(model, label, t_end_tick, hist_pass=True, fuse=True, **kw):
     t0 = time.perf_counter()
     t_cur = 0
     while t_cur < t_end_tick:
-        t_slice = min(t_end_tick, t_cur + (1 << 14))
+        t_slice = min(t_end_tick, t_cur + (TICKS >> 6))
         k, _ = sim.run(t_slice)
         steps += k
         t_cur = t_slice
-        log("[%s] t = %.5f, %d steps" % (label, t_cur / 2.0 ** 20, steps))
+        log("[%s] t = %.5f, %d steps" % (label, t_cur / TICKS, steps))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_act_sum = sim.stats().sum_n_act
@@ -746,7 +748,7 @@ def integrate_run(model, label, t_end_tick, hist_pass=True, fuse=True, **kw):
     if not hist_pass:
         rec.pop("n_act_hist_log2")
     log("[%s] %d steps to t = %.4f in %.1f s: %.4e interactions/s (whole steps), mean n_act %.0f, |dE/E| %.3e, "
-        "rule %d" % (label, steps, t_end_tick / 2.0 ** 20, wall, rec["interactions_per_s"], rec["mean_n_act"],
+        "rule %d" % (label, steps, t_end_tick / TICKS, wall, rec["interactions_per_s"], rec["mean_n_act"],
                      abs(rec["dE_over_E"]), sim.dt_rule))
     return sim, rec
 
@@ -780,7 +782,7 @@ def integrate_batched_one(model, t_end_tick, kw):
     steps = s1.steps - s0.steps
     rec = {"steps_incl_idle_replays": steps, "wall_s": wall, "interactions": s1.interactions - s0.interactions,
            "interactions_per_s": (s1.interactions - s0.interactions) / wall, "dE_over_E": (E1 - E0) / E0,
-           "dt_underflow": s1.dt_underflow, "launch": B.get_launch(), "t_end_reached": tcur[0] / 2.0 ** 20}
+           "dt_underflow": s1.dt_underflow, "launch": B.get_launch(), "t_end_reached": tcur[0] / TICKS}
     log("[mixed, one-cluster batch, graph] %d replays in %.1f s: %.4e interactions/s, |dE/E| %.3e, shape %s"
         % (steps, wall, rec["interactions_per_s"], abs(rec["dE_over_E"]), rec["launch"]))
     B.close()
@@ -791,8 +793,8 @@ def run_c2(args):
     import nbody_ics
     n = args.c2_n
     model = nbody_ics.plummer(n, 12)
-    t_end = int(args.c2_t_end * 2 ** 20)
-    log("workload: Plummer n=%d, 6th order, eta 0.1, to t = %.4f" % (n, t_end / 2.0 ** 20))
+    t_end = int(args.c2_t_end * TICKS)
+    log("workload: Plummer n=%d, 6th order, eta 0.1, to t = %.4f" % (n, t_end / TICKS))
     kw = dict(order=6, eps2=1e-8, eta=0.1, eta_start=0.01, k_min=3, k_max=20)
     runs = {}
     for label, prec, rule, fuse in (("mixed", "mixed", 0, True), ("mixed_no_fusion", "mixed", 0, False),
@@ -809,7 +811,7 @@ def run_c2(args):
         "warmup": 0, "ms_per_step": mixed["wall_s"] / max(mixed["steps"], 1) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "Plummer n=%d (seed 12), eps = 1e-4, 6th-order Hermite block steps, eta = 0.1, "
-                               "t = 0 -> %.4f" % (n, t_end / 2.0 ** 20), "n": n, "order": 6},
+                               "t = 0 -> %.4f" % (n, t_end / TICKS), "n": n, "order": 6},
         "runs": runs,
         "mixed_over_fp64_same_rule": mixed["interactions_per_s"] / runs["fp64_rule_order4"]["interactions_per_s"],
     }
@@ -821,16 +823,19 @@ def run_c3(args):
     import nbody_ics
     n_stars = args.c3_stars
     model = nbody_ics.with_bh_binary(nbody_ics.king(n_stars, 7.0, 13), 0.01, 0.2)
-    t_end = int(args.c3_t_end * 2 ** 20)
+    t_end = int(args.c3_t_end * TICKS)
     k_min = max(3, int(np.ceil(-np.log2(args.c3_t_end))))
-    log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d)"
-        % (n_stars, t_end / 2.0 ** 20, k_min))
+    log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d, k_max %d)"
+        % (n_stars, t_end / TICKS, k_min, args.c3_k_max))
     x0 = model.x[:, :2].copy()
-    kw = dict(order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1, eta_start=0.01, k_min=k_min, k_max=20)
-    sim, plain = integrate_run(model, "c3, no fusion", t_end, hist_pass=False, fuse=False, **kw)
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
+    kw = dict(order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1, eta_start=0.01, k_min=k_min,
+              k_max=args.c3_k_max)
+    plain = None
+    if args.c3_compare:
+        sim, plain = integrate_run(model, "c3, no fusion", t_end, hist_pass=False, fuse=False, **kw)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
     if args.c3_c > 0:
         sim, relat = integrate_run(model, "c3, post-Newtonian", t_end, hist_pass=False, c_light=args.c3_c,
                                    pn_terms=7, **kw)
@@ -838,7 +843,8 @@ def run_c3(args):
         del sim
         torch.cuda.empty_cache()
     sim, rec = integrate_run(model, "c3", t_end, hist_pass=False, **kw)
-    rec["without_fusion"] = {k: plain[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
+    if plain is not None:
+        rec["without_fusion"] = {k: plain[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
     if args.c3_c > 0:
         rec["post_newtonian"] = {k: relat[k] for k in ("steps", "wall_s", "interactions_per_s", "dE_over_E")}
         rec["post_newtonian"]["c_light"] = args.c3_c
@@ -854,8 +860,9 @@ def run_c3(args):
         "warmup": 0, "ms_per_step": rec["wall_s"] / max(rec["steps"], 1) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "King W0=7 %d stars (seed 13) + two 0.01-mass BHs on a circular orbit of separation "
-                               "0.2 (mutually unsoftened), eps = 1e-4, 8th-order Hermite, eta = 0.1, t = 0 -> %.5f"
-                               % (n_stars, t_end / 2.0 ** 20), "n": model.n, "order": 8},
+                               "0.2 (mutually unsoftened), eps = 1e-4, 8th-order Hermite, eta = 0.1, t = 0 -> %.5f, "
+                               "steps 2^-%d .. 2^-%d" % (n_stars, t_end / TICKS, k_min, args.c3_k_max),
+                   "n": model.n, "order": 8, "k_max": args.c3_k_max},
         "run": rec,
     }
     print(json.dumps(line), flush=True)
@@ -867,7 +874,9 @@ def main():
     ap.add_argument("--c2-n", type=int, default=131072)
     ap.add_argument("--c2-t-end", type=float, default=1.0)
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
-    ap.add_argument("--c3-t-end", type=float, default=1.0 / 256)
+    ap.add_argument("--c3-t-end", type=float, default=0.25)
+    ap.add_argument("--c3-k-max", type=int, default=30, help="c3: smallest step 2^-k_max")
+    ap.add_argument("--c3-compare", action="store_true", help="c3: also run without the fused small-block kernel")
     ap.add_argument("--c3-c", type=float, default=0.0, help="c3: also run with 1PN + 2PN + 2.5PN terms at this c")
     ap.add_argument("--micro-n", type=int, default=262144)
     ap.add_argument("--micro-orders", default="6")

@@ -17,9 +17,9 @@
  *    caller passes one workspace at create time.
  *  - 3-vector arrays are component-major [3][len]: the x components of all
  *    elements, then the y components, then the z components.
- *  - Time is an integer tick count of 2^-20 time units.  A particle on level k
- *    (k_min <= k <= k_max <= 20) has dt = 2^-k = 2^(20-k) ticks; its time is
- *    always a multiple of its dt.
+ *  - Time is an integer tick count of 2^-40 time units (int64: times up to
+ *    2^23 units).  A particle on level k (k_min <= k <= k_max <= 40) has
+ *    dt = 2^-k = 2^(40-k) ticks; its time is always a multiple of its dt.
  *  - Work is enqueued on the HIP stream given to nbody_create.  Entry points
  *    that return host values (n_act, t_next, energies) synchronise that
  *    stream; the others are asynchronous.
@@ -71,7 +71,7 @@ typedef struct {
                            outside the power for orders 6 and 8) */
     double eta_start;   /* initial step: dt0 = eta_start |a| / |jerk| */
     int32_t k_min;      /* largest step 2^-k_min */
-    int32_t k_max;      /* smallest step 2^-k_max, k_min <= k_max <= 20 */
+    int32_t k_max;      /* smallest step 2^-k_max, k_min <= k_max <= 40 */
     int32_t dt_rule;    /* time-step criterion at orders 6 and 8 (order 4 always uses Aarseth's):
                            1 = generalised Aarseth criterion of the scheme's order,
                            dt = eta (A_1 / A_(p-2))^(1/(p-3)), A_k = sqrt(|a^(k-1)||a^(k+1)|) + |a^(k)|;

@@ -34,7 +34,8 @@
  *
  * Layouts: every 3-vector array is component-major [3][n] (x[0..n) are the
  * x components, x[n..2n) the y components, ...).  Time is kept in integer
- * ticks of 2^-20 time units; a particle on level k has dt = 2^(20-k) ticks.
+ * ticks of 2^-40 time units; a particle on level k (k <= 40) has
+ * dt = 2^(40-k) ticks.
  */
 #include <math.h>
 #include <stdint.h>
@@ -44,8 +45,8 @@
 #include <omp.h>
 #endif
 
-#define TICKS_PER_UNIT (1LL << 20)
-#define LEVEL_MAX 20
+#define TICKS_PER_UNIT (1LL << 40)
+#define LEVEL_MAX 40
 
 typedef struct {
     int order;        /* 4, 6 or 8 */

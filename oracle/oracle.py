@@ -1,8 +1,8 @@
 """ctypes binding of the C oracle (nbody_oracle.c) with NumPy arrays.
 
 Test infrastructure only.  All arrays are float64, 3-vectors component-major
-with shape (3, n); times are int64 ticks of 2^-20 time units; levels int32
-(a particle on level k has dt = 2^-k).
+with shape (3, n); times are int64 ticks of 2^-40 time units; levels int32
+(a particle on level k has dt = 2^-k, k <= 40).
 """
 from __future__ import annotations
 
@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nbody_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
-TICKS_PER_UNIT = 1 << 20
+TICK_BITS = 40
+TICKS_PER_UNIT = 1 << TICK_BITS
 
 
 def lib_path() -> str:

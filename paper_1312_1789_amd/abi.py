@@ -22,6 +22,10 @@ NBODY_E_STATE = -4
 NBODY_E_UNSUPPORTED = -5
 NBODY_E_NONFINITE = -6
 
+#: time is counted in integer ticks of 2^-TICK_BITS time units
+TICK_BITS = 40
+TICKS_PER_UNIT = 1 << TICK_BITS
+
 NBODY_FP64 = 0
 NBODY_MIXED = 1
 NBODY_DS = 2

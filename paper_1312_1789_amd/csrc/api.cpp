@@ -31,7 +31,7 @@ nbody_status check_config(const nbody_config *c)
     if (!(c->eta_start > 0.0) || !std::isfinite(c->eta_start)) return fail(NBODY_E_INVALID, "eta_start must be > 0");
     if (c->dt_rule < 0 || c->dt_rule > 2) return fail(NBODY_E_INVALID, "dt_rule must be 0, 1 or 2 (got %d)", c->dt_rule);
     if (c->k_min < 0 || c->k_min > c->k_max || c->k_max > nb::kLevelMax)
-        return fail(NBODY_E_INVALID, "need 0 <= k_min <= k_max <= 20 (got %d, %d)", c->k_min, c->k_max);
+        return fail(NBODY_E_INVALID, "need 0 <= k_min <= k_max <= %d (got %d, %d)", nb::kLevelMax, c->k_min, c->k_max);
     if (!(c->c_light >= 0.0) || !std::isfinite(c->c_light)) return fail(NBODY_E_INVALID, "c_light must be finite and >= 0");
     if (c->pn_terms < 0 || c->pn_terms > 7)
         return fail(NBODY_E_INVALID, "pn_terms must be a sum of 1 (1PN), 2 (2PN) and 4 (2.5PN) (got %d)",

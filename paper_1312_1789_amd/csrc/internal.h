@@ -23,7 +23,7 @@ nbody_status check_config_checked(const nbody_config *c);
         if (e_ != hipSuccess) return nb::fail(NBODY_E_HIP, "%s: %s", #call, hipGetErrorString(e_));  \
     } while (0)
 
-constexpr int kLevelMax = 20;               // time tick = 2^-20 time units
+constexpr int kLevelMax = 40;               // time tick = 2^-40 time units; levels k <= 40
 constexpr int64_t kTicksPerUnit = int64_t(1) << kLevelMax;
 constexpr int kSchedBlock = 256;            // threads per scheduler block
 constexpr int kSchedPerThread = 4;          // particles per scheduler thread

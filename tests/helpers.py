@@ -7,7 +7,9 @@ import nbody_ics
 import oracle
 from oracle import OracleConfig
 
-TICKS = 1 << 20
+from paper_1312_1789_amd.abi import TICK_BITS, TICKS_PER_UNIT as TICKS  # noqa: E402
+
+assert TICKS == oracle.oracle.TICKS_PER_UNIT and TICK_BITS == oracle.oracle.TICK_BITS
 
 
 def say(*a):
@@ -51,7 +53,7 @@ def random_block_state(n, seed, k_min=3, k_max=20):
     rng = np.random.default_rng(seed)
     level = rng.integers(k_min, k_max + 1, n).astype(np.int32)
     T = 3 * (TICKS >> k_min) + (TICKS >> 5)
-    dt = (1 << (20 - level.astype(np.int64)))
+    dt = (1 << (TICK_BITS - level.astype(np.int64)))
     t = (T // dt) * dt
     return t.astype(np.int64), level
 

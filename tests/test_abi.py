@@ -44,7 +44,7 @@ def test_workspace_size_scales_with_n():
 
 @pytest.mark.parametrize("kw", [dict(order=5), dict(order=10), dict(precision=3), dict(n=1), dict(n_hard=2000),
                                 dict(eps2=-1.0), dict(eta=0.0), dict(eta_start=-1.0), dict(k_min=5, k_max=4),
-                                dict(k_max=21), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1),
+                                dict(k_max=41), dict(eps2=float("nan")), dict(dt_rule=3), dict(dt_rule=-1),
                                 dict(c_light=-1.0), dict(c_light=float("inf")), dict(pn_terms=8),
                                 dict(pn_terms=-1), dict(order=4, n=5000, n_hard=2000, c_light=10.0, pn_terms=1)])
 def test_config_validation(kw):

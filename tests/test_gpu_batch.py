@@ -15,7 +15,7 @@ import torch
 
 import nbody_ics
 import oracle
-from helpers import TICKS, compare_corrected, err_stats, oracle_correct, rel_err, say
+from helpers import TICK_BITS, TICKS, compare_corrected, err_stats, oracle_correct, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -52,7 +52,7 @@ def _ostate(hc, order):
 
 
 def _next(hc):
-    nxt = hc["t_tick"] + (1 << (20 - hc["level"].astype(np.int64)))
+    nxt = hc["t_tick"] + (1 << (TICK_BITS - hc["level"].astype(np.int64)))
     T = int(nxt.min())
     return T, np.nonzero(nxt == T)[0].astype(np.int32)
 

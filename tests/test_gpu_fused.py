@@ -17,7 +17,7 @@ import torch
 
 import nbody_ics
 import oracle
-from helpers import TICKS, cluster_with_bh, err_stats, oracle_force, physical_derivs, random_block_state, rel_err, say
+from helpers import TICK_BITS, TICKS, cluster_with_bh, err_stats, oracle_force, physical_derivs, random_block_state, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -39,7 +39,7 @@ def block_case():
     rng = np.random.default_rng(72)
     d = [a, j] + [rng.normal(size=(3, model.n)) * 10.0 ** (k + 2) for k in range(4)]
     t, lv = random_block_state(model.n, 73)
-    T = int((t + (1 << (20 - lv.astype(np.int64)))).min())
+    T = int((t + (1 << (TICK_BITS - lv.astype(np.int64)))).min())
     return model, eps2, n_hard, d, t, lv, T
 
 

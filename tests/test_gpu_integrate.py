@@ -13,7 +13,7 @@ import torch
 
 import nbody_ics
 import oracle
-from helpers import TICKS, compare_corrected, err_stats, oracle_correct, random_block_state, rel_err, say
+from helpers import TICK_BITS, TICKS, compare_corrected, err_stats, oracle_correct, random_block_state, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def test_schedule_exact():
         t, lv = random_block_state(model.n, seed)
         sim.load_state(model.x, model.v, [np.zeros((3, model.n))] * 2, t, lv)
         t_next, act = sim.schedule()
-        nxt = t + (1 << (20 - lv.astype(np.int64)))
+        nxt = t + (1 << (TICK_BITS - lv.astype(np.int64)))
         want_t = int(nxt.min())
         want = np.nonzero(nxt == want_t)[0]
         say("schedule n=%d n_act=%d" % (model.n, want.size))
@@ -68,10 +68,10 @@ def test_schedule_block_minima():
     cases.append((np.zeros(n, np.int64), np.full(n, 5, np.int32)))
     t = np.zeros(n, np.int64)
     lv = np.full(n, 6, np.int32)
-    lv[::7] = 8                      # block minima at 2^12 ticks, many ties per block
-    lv[5002] = 9                     # the global minimum, 2^11, in the ragged block
+    lv[::7] = 8                      # block minima at t = 2^-8, many ties per block
+    lv[5002] = 9                     # the global minimum, 2^-9, in the ragged block
     cases.append((t, lv))
-    t = np.full(n, 1 << 14, np.int64)
+    t = np.full(n, TICKS >> 6, np.int64)
     lv = np.full(n, 4, np.int32)
     lv[100:140] = 7                  # block 0: 40 ties at a larger minimum
     lv[[1500, 3100, 3101]] = 9       # the global minimum in blocks 1 and 3
@@ -80,7 +80,7 @@ def test_schedule_block_minima():
     for k, (t, lv) in enumerate(cases):
         sim.load_state(model.x, model.v, [np.zeros((3, n))] * 2, t, lv)
         t_next, act = sim.schedule()
-        nxt = t + (1 << (20 - lv.astype(np.int64)))
+        nxt = t + (1 << (TICK_BITS - lv.astype(np.int64)))
         want_t = int(nxt.min())
         want = np.nonzero(nxt == want_t)[0]
         say("schedule case %d: t_next %d, n_act %d" % (k, want_t, want.size))
@@ -99,7 +99,7 @@ def test_predict_parity(order, precision):
     d = [rng.normal(size=(3, n)) * 4.0 ** k for k in range(order - 2)]
     t, lv = random_block_state(n, 33)
     sim.load_state(model.x, model.v, d, t, lv)
-    T = int((t + (1 << (20 - lv.astype(np.int64)))).min())
+    T = int((t + (1 << (TICK_BITS - lv.astype(np.int64)))).min())
     sim.predict(T)
     got = {k: v.cpu().numpy() for k, v in sim.predicted().items()}
     os_ = oracle.State(model.m, model.x, model.v, order, d, t, lv)
@@ -149,7 +149,7 @@ def test_correct_parity(order):
     h0 = sim.to_numpy()
     ocfg = _ocfg(sim)
     os0 = _ostate(h0, order)
-    nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
+    nxt = h0["t_tick"] + (1 << (TICK_BITS - h0["level"].astype(np.int64)))
     T = int(nxt.min())
     act = np.nonzero(nxt == T)[0].astype(np.int32)
     xp, vp, ap, jp = oracle.predict(ocfg, os0, T)
@@ -176,7 +176,7 @@ def test_step_parity(order, precision):
     for step in range(10):
         h0 = sim.to_numpy()
         os0 = _ostate(h0, order)
-        nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
+        nxt = h0["t_tick"] + (1 << (TICK_BITS - h0["level"].astype(np.int64)))
         T = int(nxt.min())
         act = np.nonzero(nxt == T)[0].astype(np.int32)
         t_g, na_g = sim.step()
@@ -292,7 +292,7 @@ def test_run_equals_single_steps():
     steps_b, t_b = 0, 0
     while True:
         h = b.to_numpy()
-        nxt = int((h["t_tick"] + (1 << (20 - h["level"].astype(np.int64)))).min())
+        nxt = int((h["t_tick"] + (1 << (TICK_BITS - h["level"].astype(np.int64)))).min())
         if nxt > t_end:
             break
         t_b, _ = b.step()

@@ -20,7 +20,7 @@ import pytest
 
 import nbody_ics
 import oracle
-from helpers import TICKS, compare_corrected, oracle_correct, rel_err, say
+from helpers import TICK_BITS, TICKS, compare_corrected, oracle_correct, rel_err, say
 from oracle import OracleConfig
 
 pytestmark = pytest.mark.gpu
@@ -87,7 +87,7 @@ def test_pn_init_and_step_parity(order, precision, n_bh, terms):
         h0 = sim.to_numpy()
         os0 = oracle.State(h0["m"], h0["x"], h0["v"], order, [a.copy() for a in h0["d"]], h0["t_tick"].copy(),
                            h0["level"].copy())
-        nxt = h0["t_tick"] + (1 << (20 - h0["level"].astype(np.int64)))
+        nxt = h0["t_tick"] + (1 << (TICK_BITS - h0["level"].astype(np.int64)))
         T = int(nxt.min())
         act = np.nonzero(nxt == T)[0].astype(np.int32)
         bh_steps += int(np.sum(act < n_bh))

@@ -17,7 +17,7 @@ import pytest
 import nbody_ics
 import oracle
 from oracle import OracleConfig
-from oracle.oracle import TICKS_PER_UNIT
+from oracle.oracle import TICK_BITS, TICKS_PER_UNIT
 
 ORDERS = [4, 6, 8]
 
@@ -32,10 +32,10 @@ def test_predictor_exact_on_polynomials(oracle_lib, p):
     rng = np.random.default_rng(p)
     n = 5
     coef = rng.uniform(-1, 1, (p, 3, n))       # coef[k] = x^(k)(t0)
-    t0 = 3 * (1 << 14)
+    t0 = 3 * (TICKS_PER_UNIT >> 6)
     s = oracle.State(np.ones(n), coef[0], coef[1], p, [coef[k + 2] for k in range(p - 2)],
                      np.full(n, t0, np.int64), np.full(n, 6, np.int32))
-    t1 = t0 + 5 * (1 << 12)
+    t1 = t0 + 5 * (TICKS_PER_UNIT >> 8)
     dt = (t1 - t0) / TICKS_PER_UNIT
     xp, vp, ap, jp = oracle.predict(OracleConfig(order=p), s, t1)
 
@@ -240,23 +240,25 @@ def _quantise_brute(dtc, k_min, k_max):
     return k_max
 
 
-def test_new_level_rules(oracle_lib):
+@pytest.mark.parametrize("k_max", [20, 32, 40])
+def test_new_level_rules(oracle_lib, k_max):
     """Largest 2^-k <= dt_crit within [k_min, k_max]; at most one doubling,
-    only when the end time is a multiple of the doubled step."""
-    k_min, k_max = 3, 20
-    rng = np.random.default_rng(40)
+    only when the end time is a multiple of the doubled step (levels up to
+    40: time ticks of 2^-40)."""
+    k_min = 3
+    rng = np.random.default_rng(40 + k_max)
     for _ in range(3000):
         old = int(rng.integers(k_min, k_max + 1))
-        dt_old = 1 << (20 - old)
+        dt_old = 1 << (TICK_BITS - old)
         t1 = int(rng.integers(1, 1 << 10)) * dt_old
-        dtc = 2.0 ** rng.uniform(-23, -1)
+        dtc = 2.0 ** rng.uniform(-(k_max + 3), -1)
         want = _quantise_brute(dtc, k_min, k_max)
         if want < old:
             want = old - 1 if (old - 1 >= k_min and t1 % (2 * dt_old) == 0) else old
         assert oracle.new_level(dtc, old, t1, k_min, k_max) == want
     # exact powers of two map to themselves; NaN goes to the smallest step
-    assert oracle.new_level(2.0 ** -7, 7, 1 << 13, k_min, k_max) == 7
-    assert oracle.new_level(float("nan"), 7, 1 << 13, k_min, k_max) == k_max
+    assert oracle.new_level(2.0 ** -7, 7, 1 << (TICK_BITS - 7), k_min, k_max) == 7
+    assert oracle.new_level(float("nan"), 7, 1 << (TICK_BITS - 7), k_min, k_max) == k_max
 
 
 # --------------------------------------------------------------------------
@@ -328,7 +330,7 @@ def _check_block_invariants(cfg, s, t_end):
     sum_act = 0
     t_prev = 0
     while True:
-        nxt = s.t_tick + (1 << (20 - s.level.astype(np.int64)))
+        nxt = s.t_tick + (1 << (TICK_BITS - s.level.astype(np.int64)))
         if nxt.min() > t_end:
             break
         lvl_old = s.level.copy()
@@ -338,10 +340,10 @@ def _check_block_invariants(cfg, s, t_end):
         t_prev = t_next
         moved = s.t_tick != t_old
         assert moved.sum() == na
-        assert np.all(t_old[moved] + (1 << (20 - lvl_old[moved].astype(np.int64))) == t_next)
+        assert np.all(t_old[moved] + (1 << (TICK_BITS - lvl_old[moved].astype(np.int64))) == t_next)
         steps_per_particle += moved
         sum_act += na
-        dt = 1 << (20 - s.level.astype(np.int64))
+        dt = 1 << (TICK_BITS - s.level.astype(np.int64))
         assert np.all(s.t_tick % dt == 0)                     # t_i multiple of dt_i
         assert np.all(s.level >= lvl_old - 1)                 # at most one doubling
         assert np.all((s.level >= cfg.k_min) & (s.level <= cfg.k_max))

@@ -28,6 +28,7 @@ import pytest
 
 import oracle
 from oracle import OracleConfig
+from oracle.oracle import TICKS_PER_UNIT
 
 
 def kepler(a, e, M, E):
@@ -373,7 +374,7 @@ def test_oracle_integration_inspiral_at_peters_rate():
     st = oracle.State(m, x, v, 4)
     oracle.init(cfg, st)
     T = 16.0
-    oracle.integrate(cfg, st, int(T * (1 << 20)))
+    oracle.integrate(cfg, st, int(T * TICKS_PER_UNIT))
     r = np.linalg.norm(st.x[:, 0] - st.x[:, 1])
     w = st.v[:, 0] - st.v[:, 1]
     a1 = -M / (2.0 * (0.5 * np.dot(w, w) - M / r))

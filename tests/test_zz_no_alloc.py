@@ -11,7 +11,7 @@ import oracle
 from oracle import OracleConfig
 from paper_1312_1789_amd import Simulation, abi
 
-from helpers import random_block_state, random_derivs, rel_err, say
+from helpers import TICK_BITS, random_block_state, random_derivs, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,7 @@ def test_noalloc_matches_predict_force():
         say("noalloc case: n %d n_act %d order %d %s n_hard %d seed %d" % (n, n_act, order, prec, n_hard, seed))
         model = nbody_ics.plummer(n, seed)
         t_tick, level = random_block_state(n, seed + 1)
-        T = int((t_tick + (1 << (20 - level.astype(np.int64)))).min())
+        T = int((t_tick + (1 << (TICK_BITS - level.astype(np.int64)))).min())
         d = random_derivs(n, seed + 2, order)
         sim = Simulation(model.m, model.x, model.v, order=order, precision=prec, eps2=1e-8, n_hard=n_hard,
                          eta=0.1)
