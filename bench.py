@@ -824,12 +824,12 @@ def run_c3(args):
     n_stars = args.c3_stars
     model = nbody_ics.with_bh_binary(nbody_ics.king(n_stars, 7.0, 13), 0.01, 0.2)
     t_end = int(args.c3_t_end * TICKS)
-    k_min = max(3, int(np.ceil(-np.log2(args.c3_t_end))))
+    k_min = max(args.c3_k_min, int(np.ceil(-np.log2(args.c3_t_end))))
     log("workload: King W0=7 %d stars + BH binary, 8th order MIXED, to t = %.5f (k_min %d, k_max %d)"
         % (n_stars, t_end / TICKS, k_min, args.c3_k_max))
     x0 = model.x[:, :2].copy()
-    kw = dict(order=8, precision="mixed", eps2=1e-8, n_hard=2, eta=0.1, eta_start=0.01, k_min=k_min,
-              k_max=args.c3_k_max)
+    kw = dict(order=8, precision=args.c3_precision, eps2=1e-8, n_hard=2, eta=args.c3_eta, eta_start=0.01,
+              k_min=k_min, k_max=args.c3_k_max)
     plain = None
     if args.c3_compare:
         sim, plain = integrate_run(model, "c3, no fusion", t_end, hist_pass=False, fuse=False, **kw)
@@ -876,6 +876,11 @@ def main():
     ap.add_argument("--c3-stars", type=int, default=1 << 20)
     ap.add_argument("--c3-t-end", type=float, default=0.25)
     ap.add_argument("--c3-k-max", type=int, default=30, help="c3: smallest step 2^-k_max")
+    ap.add_argument("--c3-k-min", type=int, default=9,
+                    help="c3: largest step 2^-k_min (steps of 2^-8 or longer miss star-star passages at the "
+                         "softening length at this n; see the design notes)")
+    ap.add_argument("--c3-precision", default="mixed", choices=["mixed", "fp64", "ds"])
+    ap.add_argument("--c3-eta", type=float, default=0.1)
     ap.add_argument("--c3-compare", action="store_true", help="c3: also run without the fused small-block kernel")
     ap.add_argument("--c3-c", type=float, default=0.0, help="c3: also run with 1PN + 2PN + 2.5PN terms at this c")
     ap.add_argument("--micro-n", type=int, default=262144)
