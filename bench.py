@@ -299,6 +299,27 @@ def run_batched(args):
                "launch": {"force_grid": shape[0], "items_per_wg": shape[1], "i_tile": shape[2]},
                "cluster_time_range": [min(tcur) / TICKS, max(tcur) / TICKS]}
     h_graph = B.to_numpy()
+    # the shape of the work: over a few more batched steps, the pair
+    # evaluations done against those the i-tiles pad to (64 or 256 rows), and
+    # the share of the work in tiles of at most 16 rows
+    occ = {"steps": 0, "interactions": 0.0, "padded_64": 0.0, "padded_256": 0.0, "work_in_small_tiles": 0.0}
+    nsz = np.array(sizes, dtype=np.float64)
+    for _ in range(args.occupancy_steps):
+        B.step(1)
+        aoff = np.array(B.last_step()[0], dtype=np.int64)
+        a = np.diff(aoff).astype(np.float64)
+        occ["steps"] += 1
+        occ["interactions"] += float(np.sum(a * nsz))
+        occ["padded_64"] += float(np.sum(np.ceil(a / 64) * 64 * nsz))
+        occ["padded_256"] += float(np.sum(np.ceil(a / 256) * 256 * nsz))
+        occ["work_in_small_tiles"] += float(np.sum(np.where(a % 64 <= 16, (a % 64) * nsz, 0.0)))
+    if occ["steps"]:
+        log("[batched] work over %d more steps: %.3e interactions; tiles of 64 rows padded to %.3e (%.1f%% used), "
+            "of 256 rows to %.3e (%.1f%% used); %.1f%% of the work in tiles of at most 16 rows"
+            % (occ["steps"], occ["interactions"], occ["padded_64"], 100 * occ["interactions"] / occ["padded_64"],
+               occ["padded_256"], 100 * occ["interactions"] / occ["padded_256"],
+               100 * occ["work_in_small_tiles"] / occ["interactions"]))
+    batched["work_shape"] = occ
     del B
     # the same steps launched eagerly (no graph)
     E = Batch(clusters, precision="mixed", **kw)
@@ -903,6 +924,7 @@ def main():
     ap.add_argument("--warm-time", type=float, default=1.0 / 64, help="batched: integrate to this time first")
     ap.add_argument("--autotune-steps", type=int, default=2, help="batched: steps per autotuned shape (0 = off)")
     ap.add_argument("--skip-per-cluster", action="store_true", help="batched: skip the one-context-per-cluster run")
+    ap.add_argument("--occupancy-steps", type=int, default=20, help="batched: steps whose active counts are tallied")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)

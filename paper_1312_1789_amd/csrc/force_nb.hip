@@ -13,10 +13,14 @@
 // holds their indices in increasing order.
 //
 // Kernel 1, grid (i-tiles of kNbBlock rows, j-splits): each lane holds one
-// active row and walks its split through LDS tiles of kNbBlock records in
-// increasing j, adding the pair terms of the non-neighbours (the neighbours
-// are masked out of the same FMA sequence as the full force) and appending
-// the neighbours to its split's part of the list.  Kernel 2, one wave per
+// active row and walks its split in increasing j, adding the pair terms of
+// the non-neighbours (the neighbours are masked out of the same FMA sequence
+// as the full force) and appending the neighbours to its split's part of the
+// list.  The j below n_hard (unsoftened when i is hard too) are taken one by
+// one with their checks; the rest streams through LDS tiles of kNbBlock
+// records with no per-pair index test: the self pair (difference zero, r^2 =
+// eps^2 > 0) either is a neighbour, and is dropped at the append, or adds
+// exact zeros to the regular part.  Kernel 2, one wave per
 // row: the regular partial sums added in split order, the split lists
 // concatenated, and the irregular part summed over the list (lanes take
 // every 64th entry, then a fixed butterfly).  A row whose list was cut at
@@ -44,6 +48,38 @@ __device__ __forceinline__ bool nb_pair(const typename PolF64<4, false>::I &i, c
     const double rinv = rsqrt64(ok ? r2 : 1.0);
     const double mr = ok ? j.m * rinv : 0.0;
     core_fma<4, false, double>(dx, dy, dz, wx, wy, wz, 0, 0, 0, 0, 0, 0, mr, rinv * rinv, A);
+    return is_nb;
+}
+
+// The pair of the LDS-tile loop: softened (eps2 > 0, so r^2 > 0), no
+// validity test (the self pair is handled as stated above).
+__device__ __forceinline__ bool nb_pair_soft(const typename PolF64<4, false>::I &i, const RecF64<4> &j, double e2,
+                                             double hh_e, double *A)
+{
+    const double dx = j.x - i.x, dy = j.y - i.y, dz = j.z - i.z;
+    const double wx = j.vx - i.vx, wy = j.vy - i.vy, wz = j.vz - i.vz;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, e2)));
+    const bool is_nb = r2 < hh_e;
+    const double rinv = rsqrt64(r2);
+    const double mr = is_nb ? 0.0 : j.m * rinv;
+    core_fma<4, false, double>(dx, dy, dz, wx, wy, wz, 0, 0, 0, 0, 0, 0, mr, rinv * rinv, A);
+    return is_nb;
+}
+
+__device__ __forceinline__ bool nb_pair_soft(const typename DSIn<4>::I &i, const RecDS<4> &j, float e2, float hh_e,
+                                             float *A)
+{
+    const float dx = (j.xh - i.xh) + (j.xl - i.xl);
+    const float dy = (j.yh - i.yh) + (j.yl - i.yl);
+    const float dz = (j.zh - i.zh) + (j.zl - i.zl);
+    const float wx = (j.vxh - i.vxh) + (j.vxl - i.vxl);
+    const float wy = (j.vyh - i.vyh) + (j.vyl - i.vyl);
+    const float wz = (j.vzh - i.vzh) + (j.vzl - i.vzl);
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, e2)));
+    const bool is_nb = r2 < hh_e;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float mr = is_nb ? 0.0f : j.m * rinv;
+    core_fma<4, false, float>(dx, dy, dz, wx, wy, wz, 0, 0, 0, 0, 0, 0, mr, rinv * rinv, A);
     return is_nb;
 }
 
@@ -93,33 +129,46 @@ k_force_nb(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *
         acc[c] = 0.0;
         zero_part(p[c]);
     }
-    constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk : (1 << 30);
-    int since = 0;   // pairs since the last flush (the same in every lane)
+    static_assert(Pol::kChunk == 0 || Pol::kChunk == kNbBlock, "one FP32 chunk per tile");
     int cnt = 0;
     int32_t *my_seg = seg + (int64_t(split) * n_act + qq) * max_nb;
+    // j below n_hard: each pair's terms added into FP64 on their own
+    const int64_t jh1 = j1 < n_hard ? j1 : n_hard;
+    for (int64_t j = j0; j < jh1; ++j) {
+        const Rec rj = rec[j];
+        Part ph[13];
+#pragma unroll
+        for (int c = 0; c < 13; ++c) zero_part(ph[c]);
+        const bool is_nb = nb_pair(ip, rj, i_hard ? ET(0) : e2, i_hard ? hh_0 : hh_e, j != i, ph);
+        if (is_nb) {
+            if (row && cnt < max_nb) my_seg[cnt] = int32_t(j);
+            ++cnt;
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += to_double(ph[c]);
+    }
+    // the rest (softened pairs) through LDS tiles; the FP32 sums are flushed
+    // after every tile (one chunk)
     __shared__ Rec tile[kNbBlock];
-    for (int64_t jt = j0; jt < j1; jt += kNbBlock) {
+    const int64_t js0 = j0 > n_hard ? j0 : n_hard;
+    for (int64_t jt = js0; jt < j1; jt += kNbBlock) {
         const int64_t jl = jt + threadIdx.x;
         if (jl < j1) tile[threadIdx.x] = rec[jl];
         __syncthreads();
         const int m = j1 - jt < kNbBlock ? int(j1 - jt) : kNbBlock;
         for (int u = 0; u < m; ++u) {
             const Rec rj = tile[u];
-            const int64_t j = jt + u;
-            const bool hard = i_hard && j < n_hard;
-            const bool is_nb = nb_pair(ip, rj, hard ? ET(0) : e2, hard ? hh_0 : hh_e, j != i, p);
-            if (is_nb) {
-                if (row && cnt < max_nb) my_seg[cnt] = int32_t(j);
-                ++cnt;
-            }
-            if (++since == CH) {
-                flush<Part, 1>(&p, &acc);
-                since = 0;
+            if (nb_pair_soft(ip, rj, e2, hh_e, p)) {
+                const int64_t j = jt + u;
+                if (j != i) {
+                    if (row && cnt < max_nb) my_seg[cnt] = int32_t(j);
+                    ++cnt;
+                }
             }
         }
+        flush<Part, 1>(&p, &acc);
         __syncthreads();
     }
-    flush<Part, 1>(&p, &acc);
     if (!row) return;
 #pragma unroll
     for (int c = 0; c < 6; ++c) part[(int64_t(split) * 6 + c) * n_act + q] = acc[c];
