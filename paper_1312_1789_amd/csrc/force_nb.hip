@@ -170,13 +170,16 @@ k_force_nb(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t *
         __syncthreads();
     }
     if (!row) return;
+    // split-fastest: the finishing kernel's lanes read consecutive splits
+    const int n_split = int(gridDim.y);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) part[(int64_t(split) * 6 + c) * n_act + q] = acc[c];
-    seg_cnt[int64_t(split) * n_act + q] = cnt;
+    for (int c = 0; c < 6; ++c) part[(int64_t(c) * n_act + q) * n_split + split] = acc[c];
+    seg_cnt[q * n_split + split] = cnt;
 }
 
-// One 64-lane workgroup per active row: lanes 0..5 add the row's regular
-// partial sums over the splits in order; all lanes copy the splits'
+// One 64-lane workgroup per active row: for each of the 6 regular
+// components, lane l adds the row's partial sums of splits l, l + 64, ... in
+// order and a fixed butterfly folds the lanes; all lanes copy the splits'
 // neighbour lists one after the other (increasing j, at most max_nb entries);
 // then lane l adds the irregular terms of list entries l, l + 64, ... and the
 // lanes' sums are folded with a fixed butterfly.
@@ -192,30 +195,46 @@ k_nb_finish(const typename Pol::Rec *__restrict__ rec, int64_t n, const int32_t 
     using Part = typename Pol::Part;
     const int64_t q = blockIdx.x;
     const int l = int(threadIdx.x);
-    if (l < 6) {
-        // the loads of eight splits in flight together, added in split order
-        const double *src = part + int64_t(l) * n_act + q;
-        const int64_t step = 6 * n_act;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        // the loads of eight of this lane's splits in flight together, added in split order
+        const double *src = part + (int64_t(c) * n_act + q) * n_split;
         double s = 0.0;
-        int sp = 0;
-        for (; sp + 8 <= n_split; sp += 8) {
+        int sp = l;
+        for (; sp + 7 * 64 < n_split; sp += 8 * 64) {
             double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[int64_t(sp + u) * step];
+            for (int u = 0; u < 8; ++u) v[u] = src[sp + u * 64];
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += v[u];
         }
-        for (; sp < n_split; ++sp) s += src[int64_t(sp) * step];
-        (l < 3 ? acc_reg : jrk_reg)[(l % 3) * n_act + q] = s;
+        for (; sp < n_split; sp += 64) s += src[sp];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+        if (l == 0) (c < 3 ? acc_reg : jrk_reg)[(c % 3) * n_act + q] = s;
     }
     // the lists: 64 splits at a time, lane l taking split s0 + l; a prefix sum
     // over the lanes places each split's entries after those of the splits
-    // before it, and at most max_nb entries are kept in all
+    // before it, and at most max_nb entries are kept in all.  The counts of
+    // up to kNbPass passes are loaded together first (one memory round trip
+    // for them instead of one per pass).
+    constexpr int kNbPass = 16;
     int64_t total = 0;
     int written = 0;
+    int cnts[kNbPass];
     for (int s0 = 0; s0 < n_split; s0 += 64) {
+        const int pass = (s0 / 64) % kNbPass;
+        if (pass == 0) {
+#pragma unroll
+            for (int k = 0; k < kNbPass; ++k) {
+                const int spk = s0 + 64 * k + l;
+                cnts[k] = spk < n_split ? seg_cnt[q * n_split + spk] : 0;
+            }
+        }
         const int sp = s0 + l;
-        const int c = sp < n_split ? seg_cnt[int64_t(sp) * n_act + q] : 0;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < kNbPass; ++k) c = k == pass ? cnts[k] : c;
         const int stored = c < max_nb ? c : max_nb;
         int incl = stored;
 #pragma unroll
@@ -292,9 +311,9 @@ int64_t nb_scratch_per_row(int max_nb) { return 6 * 8 + 4 + 4 * int64_t(max_nb);
 int nb_split(int64_t n, int64_t n_act, int max_nb, int64_t scratch_bytes, int n_split_req)
 {
     const int64_t tiles = (n_act + kNbBlock - 1) / kNbBlock;
-    // about 2048 workgroups of 128 lanes (8 waves per SIMD), splits of at
-    // least one tile, and what the scratch holds
-    int64_t sp = n_split_req > 0 ? n_split_req : (2048 + tiles - 1) / tiles;
+    // about 4096 workgroups of 128 lanes (8 waves per SIMD; the kernel fits
+    // 6 at a time), splits of at least one tile, and what the scratch holds
+    int64_t sp = n_split_req > 0 ? n_split_req : (4096 + tiles - 1) / tiles;
     const int64_t by_n = (n + kNbBlock - 1) / kNbBlock;
     const int64_t by_scratch = scratch_bytes / (nb_scratch_per_row(max_nb) * (n_act > 0 ? n_act : 1));
     if (sp > by_n) sp = by_n;
