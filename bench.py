@@ -302,7 +302,8 @@ def run_batched(args):
     # the shape of the work: over a few more batched steps, the pair
     # evaluations done against those the i-tiles pad to (64 or 256 rows), and
     # the share of the work in tiles of at most 16 rows
-    occ = {"steps": 0, "interactions": 0.0, "padded_64": 0.0, "padded_256": 0.0, "work_in_small_tiles": 0.0}
+    occ = {"steps": 0, "interactions": 0.0, "padded_64": 0.0, "padded_256": 0.0, "padded_64_pow2_tail": 0.0,
+           "work_in_small_tiles": 0.0}
     nsz = np.array(sizes, dtype=np.float64)
     for _ in range(args.occupancy_steps):
         B.step(1)
@@ -312,12 +313,18 @@ def run_batched(args):
         occ["interactions"] += float(np.sum(a * nsz))
         occ["padded_64"] += float(np.sum(np.ceil(a / 64) * 64 * nsz))
         occ["padded_256"] += float(np.sum(np.ceil(a / 256) * 256 * nsz))
+        # 64-row tiles with each cluster's last tile cut to the next power of two of its rows
+        rem = a % 64
+        tail = np.where(rem > 0, 2.0 ** np.ceil(np.log2(np.maximum(rem, 1))), 0.0)
+        occ["padded_64_pow2_tail"] += float(np.sum((np.floor(a / 64) * 64 + tail) * nsz))
         occ["work_in_small_tiles"] += float(np.sum(np.where(a % 64 <= 16, (a % 64) * nsz, 0.0)))
     if occ["steps"]:
         log("[batched] work over %d more steps: %.3e interactions; tiles of 64 rows padded to %.3e (%.1f%% used), "
-            "of 256 rows to %.3e (%.1f%% used); %.1f%% of the work in tiles of at most 16 rows"
+            "of 256 rows to %.3e (%.1f%% used), of 64 rows with power-of-two last tiles to %.3e (%.1f%% used); "
+            "%.1f%% of the work in tiles of at most 16 rows"
             % (occ["steps"], occ["interactions"], occ["padded_64"], 100 * occ["interactions"] / occ["padded_64"],
-               occ["padded_256"], 100 * occ["interactions"] / occ["padded_256"],
+               occ["padded_256"], 100 * occ["interactions"] / occ["padded_256"], occ["padded_64_pow2_tail"],
+               100 * occ["interactions"] / occ["padded_64_pow2_tail"],
                100 * occ["work_in_small_tiles"] / occ["interactions"]))
     batched["work_shape"] = occ
     del B

@@ -6,19 +6,19 @@
 
 namespace nb {
 
-constexpr int kBatchMaxItems = 16384;  // most work items the plan aims for in one step
-constexpr int kBatchMaxPerWG = 16;     // most items aimed for per persistent workgroup
-constexpr int kBatchITileMax = 256;   // largest i-tile: active rows per work item (= force workgroup size)
+constexpr int kBatchITileMax = 256;   // largest i-tile: active rows per work item
+constexpr int64_t kBatchMaxRows = int64_t(1) << 22;   // items aimed for in one step x i-tile, at most
+constexpr int kBatchMaxPerWG = 32;     // most items aimed for per persistent workgroup
 constexpr int kBatchSchedBlock = 1024;  // particles per scheduling block
+constexpr int kXcds = 8;                // XCDs of the device: work queues of the persistent force kernel
 
 // Written by the plan kernel of every batched step and read by the kernels
 // after it.  Arrays sized n_clusters + 1 (the last entry of a scanned array
 // holds its total).
 struct BatchPlan {
-    unsigned long long queue;   // next work item of the persistent force kernel
     int64_t t_end;              // clusters whose next time exceeds this do not step
     int64_t n_live;             // clusters that stepped in the last plan
-    int64_t pad[5];
+    int64_t pad[6];
     int64_t *nact;              // [nc]   active particles per cluster
     int64_t *aoff;              // [nc+1] offsets of the clusters' active lists
     int64_t *ioff;              // [nc+1] first work item of each cluster rank
@@ -26,6 +26,9 @@ struct BatchPlan {
     int64_t *jchunk;            // [nc]   j-range per split
     int32_t *split;             // [nc]   j-splits per cluster
     int64_t *tcur;              // [nc]   time of the cluster's last completed step
+    // items taken from each XCD's eighth of the step's items (one 64-byte
+    // line per counter); reset by the plan
+    unsigned long long queue[kXcds * 8];
 };
 
 struct BatchCounters {
@@ -58,7 +61,7 @@ struct BatchLaunch {
     int64_t n_hard;             // per cluster; every pair is unsoftened when eps2 == 0
     int force_grid;             // workgroups of the persistent force kernel
     int per_wg;                 // work items aimed for per persistent workgroup
-    int k_items;                // items aimed for in one step: min(force_grid * per_wg, kBatchMaxItems)
+    int k_items;                // items aimed for in one step: min(force_grid * per_wg, kBatchMaxRows / itile)
     int itile;                  // active rows per work item: 64 or 256
 };
 
@@ -66,7 +69,7 @@ hipError_t batch_cid(const BatchLaunch &L, hipStream_t s);
 hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_active, int order, hipStream_t s);
 hipError_t batch_predict(const BatchLaunch &L, const nbody_state &st, int order, int precision, void *rec,
                          hipStream_t s);
-// Reset the work queue (a second force pass on the same plan).
+// Reset the work queues (a second force pass on the same plan).
 hipError_t batch_requeue(const BatchLaunch &L, hipStream_t s);
 hipError_t batch_force(const BatchLaunch &L, int order, int precision, const void *rec, hipStream_t s);
 hipError_t batch_reduce(const BatchLaunch &L, int order, double *o0, double *o1, double *o2, double *o3,

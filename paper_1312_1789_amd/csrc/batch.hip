@@ -9,11 +9,11 @@
 //                        the cluster's t_next, active counts;
 //   k_b_plan             one block: active offsets, j-splits and work items
 //                        per cluster (largest clusters first), counters, and
-//                        the reset of the work queue;
+//                        the reset of the work queues;
 //   k_b_compact          ordered active lists;
 //   k_b_predict          every particle to its cluster's t_next;
-//   k_b_force            persistent: workgroups pull (cluster, i-tile, j-split)
-//                        items from a device queue until it is empty;
+//   k_b_force            persistent: workgroups take (cluster, i-tile, j-split)
+//                        items from per-XCD queues until all are empty;
 //   k_b_reduce           split partials summed in split order;
 //   k_b_correct          corrector, interpolation and new steps.
 // Method as in the single-system kernels (paper: Abstract; Sec. "Codes
@@ -29,6 +29,7 @@ namespace nb {
 namespace {
 
 constexpr int kBBlock = kBatchSchedBlock;
+constexpr int kBTile = 32;   // records per LDS tile of the one-wave force workgroups
 constexpr int kBThreads = 256;  // threads per scheduling block (4 particles each)
 
 __device__ __forceinline__ int64_t b_next(const int64_t *t_tick, const int32_t *level, int64_t i)
@@ -154,7 +155,7 @@ __device__ int64_t block_sum(int64_t v, int64_t *sh)
 // persistent kernel ends evenly.  Items are numbered in the cluster order
 // ord[] (largest clusters first).  Bound used for the partial buffer:
 // s_c <= itile N_c k_items / W + 1, so sum_c s_c a_c <= itile k_items + n.
-// Also resets the work queue and adds the step's interactions to the counters.
+// Also resets the work queues and adds the step's interactions to the counters.
 __global__ void __launch_bounds__(kBThreads)
 k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ ord, const int64_t *__restrict__ tnext,
          BatchPlan *__restrict__ pl, int ncomp, int k_items, int itile, BatchCounters *__restrict__ ctr)
@@ -193,8 +194,8 @@ k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ or
     __syncthreads();
     block_scan(pl->ioff, nc, sh);
     block_scan(pl->poff, nc, sh);
+    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 8] = 0;
     if (threadIdx.x == 0) {
-        pl->queue = 0;
         pl->n_live = live;
         ctr->interactions += inter;
         ctr->sum_n_act += pl->aoff[nc];
@@ -277,14 +278,178 @@ k_b_predict(int64_t n, const int32_t *__restrict__ cid, const int64_t *__restric
     predict_one<P, PREC>(n, i, dt, m, x, v, ds, rec_out);
 }
 
-// Persistent force kernel.  Each workgroup takes items from the queue until
-// it is empty; item r (in cluster rank order) is (cluster ord[rank], i-tile,
-// j-split).  Every wave reaches the exit: the queue only grows.  With 64-row
-// tiles, a tile of at most 16 active rows spreads each row over several
-// lanes (the wave j-split of the single-system kernel C) instead of leaving
-// most lanes idle.
-template <class Pol, int P, int BLOCK, int TILE>
-__global__ void __launch_bounds__(BLOCK)
+// One work item of a 64-lane workgroup: the rows of one i-tile against the
+// j-range [j0, j1) of its cluster (cluster particles [base, base + nn), the
+// first nh unsoftened).  The 64 lanes form R = 64 / JS groups of JS
+// consecutive lanes; group r holds the tile's rows r and r + R (two rows per
+// lane, so one record read from LDS serves two rows) and lane sl of the group
+// takes j0 + sl, j0 + sl + JS, ... .  The JS lanes' sums are folded with a
+// fixed butterfly and lane sl = 0 stores the group's rows.  A tile of `rows`
+// active rows takes the largest JS with 2R >= rows, so a cluster's last,
+// partly filled tile leaves at most half of its lanes idle.
+template <class Pol, int P, int JS, int TILE>
+__device__ __forceinline__ void b_item(const typename Pol::Rec *__restrict__ rec, const int32_t *__restrict__ al,
+                                       int64_t na, int64_t row0, int64_t base, int64_t nn, int64_t nh, int64_t j0,
+                                       int64_t j1, typename Pol::ET e2, typename Pol::Rec (*tile)[TILE],
+                                       double *__restrict__ dst)
+{
+    using Rec = typename Pol::Rec;
+    using Part = typename Pol::Part;
+    using ET = typename Pol::ET;
+    static_assert(!Pol::kWithPot, "the batched force sums no potential");
+    static_assert(TILE % JS == 0, "tile shape");
+    constexpr int R = 64 / JS;
+    constexpr int NV = 3 * (P / 2);
+    constexpr int PIECES = int(sizeof(Rec) / 16);       // 16-byte pieces per record
+    constexpr int PER_T = (TILE * PIECES + 63) / 64;     // pieces each lane moves per tile
+    constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk / JS : (1 << 30);   // a lane's j per FP32 chunk
+    typedef uint4 __attribute__((may_alias)) piece_t;
+    const int lane = int(threadIdx.x);
+    const int r = lane / JS, sl = lane % JS;
+    typename Pol::I ip[2];
+    int64_t iidx[2];
+    double acc[2][NV];
+    Part pt[2][13];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int64_t q0 = row0 + r + k * R;
+        const int64_t q = q0 < na ? q0 : na - 1;   // padding rows recompute the last row; never stored
+        const int64_t ia = al[q];
+        iidx[k] = (ia >= base && ia < base + nn) ? ia : base;
+        ip[k] = Pol::load(rec[iidx[k]]);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[k][c] = 0.0;
+    }
+    // unsoftened pairs among the cluster's first nh particles: this lane's j
+    // of [j0, min(j1, base + nh)), each added into FP64 on its own
+    const int64_t jh1 = j1 < base + nh ? j1 : base + nh;
+    for (int64_t j = j0 + sl; j < jh1; j += JS) {
+        const Rec rj = rec[j];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            Part ph[13];
+#pragma unroll
+            for (int c = 0; c < 13; ++c) zero_part(ph[c]);
+            const ET el = (iidx[k] - base < nh) ? ET(0) : e2;
+            Pol::template pair<true>(ip[k], rj, el, j != iidx[k], ph);
+#pragma unroll
+            for (int c = 0; c < NV; ++c) acc[k][c] += to_double(ph[c]);
+        }
+    }
+    // the softened rest through double-buffered LDS tiles; slots of the last
+    // tile past j1 hold zero records (mass 0), which add exact zeros, as does
+    // the row's own particle (zero separation, softened r^2 > 0)
+    const int64_t js0 = j0 > base + nh ? j0 : base + nh;
+    piece_t pre[PER_T];
+    auto fetch = [&](int64_t jt) {
+        const piece_t *src = reinterpret_cast<const piece_t *>(rec + jt);
+        const int64_t avail = (j1 - jt) * PIECES;
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            const int pc = lane + k * 64;
+            if (pc < avail && pc < TILE * PIECES) pre[k] = src[pc];
+            else pre[k] = piece_t{0u, 0u, 0u, 0u};
+        }
+    };
+    if (js0 < j1) fetch(js0);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < 13; ++c) zero_part(pt[k][c]);
+    // every tile is taken whole (IT records per lane): the slots of the last
+    // tile past j1 hold zero records.  The FP32 sums are added into FP64
+    // every kChunk / TILE tiles (kChunk consecutive j of the range).
+    constexpr int IT = TILE / JS;
+    constexpr int FL = Pol::kChunk > 0 ? Pol::kChunk / TILE : (1 << 30);
+    static_assert(Pol::kChunk % TILE == 0, "whole tiles per FP32 chunk");
+    int since = 0;   // tiles since the last flush
+    int buf = 0;
+    for (int64_t jt = js0; jt < j1; jt += TILE) {
+        piece_t *tw = reinterpret_cast<piece_t *>(tile[buf]);
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+            if (lane + k * 64 < TILE * PIECES) tw[lane + k * 64] = pre[k];
+        __syncthreads();   // tile ready; the other buffer is no longer read
+        if (jt + TILE < j1) fetch(jt + TILE);
+        const Rec *tr = tile[buf] + sl;
+#pragma unroll 8
+        for (int u = 0; u < IT; ++u) {
+            const Rec rj = tr[u * JS];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) Pol::template pair<false>(ip[k], rj, e2, true, pt[k]);
+        }
+        if (++since == FL) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) {
+                    acc[k][c] += to_double(pt[k][c]);
+                    zero_part(pt[k][c]);
+                }
+            since = 0;
+        }
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[k][c] += to_double(pt[k][c]);
+    // fold the group's JS lanes (consecutive lanes: xor offsets below JS stay in the group)
+#pragma unroll
+    for (int m = JS / 2; m > 0; m >>= 1)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) acc[k][c] += __shfl_xor(acc[k][c], m, 64);
+    if (sl == 0) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t q0 = row0 + r + k * R;
+            if (q0 < na)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) dst[int64_t(c) * na + q0] = acc[k][c];
+        }
+    }
+}
+
+// b_item with the largest lane group JS (at most 64 and the tile length)
+// whose 2 * 64 / JS rows hold the tile's `rows` active rows.
+template <class Pol, int P, int TILE, int ROWS>
+__device__ __forceinline__ void b_item_rows(int rows, const typename Pol::Rec *__restrict__ rec,
+                                            const int32_t *__restrict__ al, int64_t na, int64_t row0, int64_t base,
+                                            int64_t nn, int64_t nh, int64_t j0, int64_t j1, typename Pol::ET e2,
+                                            typename Pol::Rec (*tile)[TILE], double *__restrict__ dst)
+{
+    constexpr int J2 = 2 < TILE ? 2 : TILE, J4 = 4 < TILE ? 4 : TILE, J8 = 8 < TILE ? 8 : TILE;
+    constexpr int J16 = 16 < TILE ? 16 : TILE, J32 = 32 < TILE ? 32 : TILE, J64 = 64 < TILE ? 64 : TILE;
+    if (ROWS == 128 && rows > 64) b_item<Pol, P, 1, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else if (rows > 32) b_item<Pol, P, J2, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else if (rows > 16) b_item<Pol, P, J4, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else if (rows > 8) b_item<Pol, P, J8, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else if (rows > 4) b_item<Pol, P, J16, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else if (rows > 2) b_item<Pol, P, J32, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    else b_item<Pol, P, J64, TILE>(rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+}
+
+// Persistent force kernel.  The step's items (in cluster rank order: item
+// = cluster ord[rank], i-tile, j-split) form 8 contiguous ranges, one per
+// XCD, each with its own queue counter.  The dispatcher places workgroup g on
+// XCD g mod 8: a workgroup takes items from its own XCD's range (a few
+// clusters, whose j records that XCD's L2 then holds), then from the other
+// ranges in turn, and leaves when all eight are empty.  Each counter is
+// shared by an eighth of the workgroups only.  Every wave reaches the exit:
+// the counters only grow.  Tiles of ROWS = 64 or 128 rows run as one wave
+// with two rows per lane (b_item); 256-row tiles as four waves with one row
+// per lane.
+
+// Waves per SIMD the register allocation of k_b_force aims for: the
+// one-wave workgroups of the FP32 pair arithmetic (MIXED) at orders 4 and 6
+// fit 3 without spills (otherwise the compiler's own choice).
+template <class Pol, int P, int BLOCK>
+constexpr int b_waves() { return (BLOCK == 64 && sizeof(typename Pol::Part) == 4 && P <= 6) ? 3 : 1; }
+
+template <class Pol, int P, int BLOCK, int TILE, int ROWS>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(b_waves<Pol, P, BLOCK>())))
 k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
           int nc, const int32_t *__restrict__ act, BatchPlan *__restrict__ pl, double eps2, int64_t n_hard,
           int ncomp, double *__restrict__ part)
@@ -292,98 +457,73 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__
     using Rec = typename Pol::Rec;
     using ET = typename Pol::ET;
     __shared__ Rec tile[2][TILE];
-    __shared__ int64_t s_item;
+    __shared__ int64_t s_take;
     const ET e2 = ET(eps2);
     const int64_t total = pl->ioff[nc];
-    for (;;) {
-        __syncthreads();   // previous item's tiles and s_item no longer read
-        if (threadIdx.x == 0) s_item = int64_t(atomicAdd(&pl->queue, 1ull));
-        __syncthreads();
-        const int64_t item = s_item;
-        if (item >= total) break;
-        // rank of the item's cluster: ioff[rank] <= item < ioff[rank + 1]
-        int lo = 0, hi = nc;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) / 2;
-            if (pl->ioff[mid] <= item) lo = mid; else hi = mid;
-        }
-        const int c = ord[lo];
-        const int64_t local = item - pl->ioff[lo];
-        const int sp = pl->split[c];
-        const int64_t tile_i = local / sp, split = local % sp;
-        const int64_t na = pl->nact[c], base = off[c], nn = off[c + 1] - base;
-        const int64_t jc = pl->jchunk[c];
-        const int64_t j0 = base + split * jc;
-        const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
-        const int64_t nh = n_hard < nn ? n_hard : nn;
-        const int64_t rows = (na - tile_i * BLOCK < BLOCK) ? na - tile_i * BLOCK : BLOCK;
-        if (BLOCK == 64 && rows <= 16) {
-            // few active rows in this tile: 1, 4 or 16 rows, each spread over
-            // 64, 16 or 4 lanes that take interleaved j (the split's range),
-            // folded across those lanes with a fixed butterfly
-            const int R = rows <= 1 ? 1 : (rows <= 4 ? 4 : 16);
-            const int JS = 64 / R;
-            const int r = int(threadIdx.x) / JS, sl = int(threadIdx.x) % JS;
-            const int64_t qw = tile_i * BLOCK + r;
-            const int64_t qc = qw < na ? qw : na - 1;
-            const int64_t ia = act[pl->aoff[c] + qc];
-            const int64_t i = (ia >= base && ia < base + nn) ? ia : base;
-            const typename Pol::I ipw = Pol::load(rec[i]);
-            const bool i_hard = i - base < nh;
-            using Part = typename Pol::Part;
-            double aw[13];
-            Part pw[13];
-#pragma unroll
-            for (int cc = 0; cc < 13; ++cc) {
-                aw[cc] = 0.0;
-                zero_part(pw[cc]);
+    const int x0 = int(blockIdx.x) % kXcds;
+    for (int v = 0; v < kXcds; ++v) {
+        const int xr = (x0 + v) % kXcds;
+        const int64_t r0 = total * xr / kXcds, len = total * (xr + 1) / kXcds - r0;
+        unsigned long long *q = &pl->queue[xr * 8];
+        for (;;) {
+            __syncthreads();   // the previous item's tiles and s_take are no longer read
+            if (threadIdx.x == 0) {
+                // an exhausted range is seen with a load, without adding to its counter
+                const unsigned long long seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_take = seen >= (unsigned long long)len ? len : int64_t(atomicAdd(q, 1ull));
             }
-            constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk : (1 << 30);
-            int since = 0;
-            int64_t j = j0 + sl;
-            Rec nxt = rec[j < j1 ? j : j1 - 1];
-            for (; j < j1; j += JS) {
-                const Rec rj = nxt;
-                nxt = rec[j + JS < j1 ? j + JS : j1 - 1];
-                const ET el = (i_hard && j - base < nh) ? ET(0) : e2;
-                Pol::template pair<true>(ipw, rj, el, j != i, pw);
-                if (++since == CH) {
-                    flush<Part, 1>(&pw, &aw);
-                    since = 0;
+            __syncthreads();
+            // the same value in every lane: made scalar, so that everything
+            // derived from it (cluster, ranges, loop bounds) stays in SGPRs
+            const uint64_t tv = uint64_t(s_take);
+            const uint32_t th = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(tv >> 32)));
+            const uint32_t tl = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(tv)));
+            const int64_t take = int64_t((uint64_t(th) << 32) | tl);
+            if (take >= len) break;
+            const int64_t item = r0 + take;
+            // rank of the item's cluster: ioff[lo] <= item < ioff[lo + 1]
+            int lo = 0, hi = nc;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (pl->ioff[mid] <= item) lo = mid; else hi = mid;
+            }
+            const int c = ord[lo];
+            const int64_t local = item - pl->ioff[lo];
+            const int sp = pl->split[c];
+            const int64_t tile_i = local / sp, split = local % sp;
+            const int64_t na = pl->nact[c], base = off[c], nn = off[c + 1] - base;
+            const int64_t jc = pl->jchunk[c];
+            const int64_t j0 = base + split * jc;
+            const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
+            const int64_t nh = n_hard < nn ? n_hard : nn;
+            double *dst = part + pl->poff[c] + split * ncomp * na;
+            const int32_t *al = act + pl->aoff[c];
+            if constexpr (BLOCK == 64) {
+                const int64_t row0 = tile_i * ROWS;
+                const int64_t rows = na - row0 < ROWS ? na - row0 : ROWS;
+                b_item_rows<Pol, P, TILE, ROWS>(int(rows), rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+            } else {
+                // this lane's active row
+                const int64_t q0 = tile_i * BLOCK + threadIdx.x;
+                const int64_t q = q0 < na ? q0 : na - 1;
+                typename Pol::I ip[1];
+                int64_t iidx[1];
+                double acc[1][13];
+                {
+                    const int64_t ia = al[q];
+                    iidx[0] = (ia >= base && ia < base + nn) ? ia : base;
+                    ip[0] = Pol::load(rec[iidx[0]]);
+#pragma unroll
+                    for (int cc = 0; cc < 13; ++cc) acc[0][cc] = 0.0;
+                }
+                hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
+                const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
+                lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
+                if (q0 < na) {
+#pragma unroll
+                    for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + q0] = acc[0][cc];
                 }
             }
-            flush<Part, 1>(&pw, &aw);
-            for (int m = JS / 2; m > 0; m >>= 1)
-#pragma unroll
-                for (int cc = 0; cc < 13; ++cc) aw[cc] += __shfl_xor(aw[cc], m, 64);
-            if (sl == 0 && r < rows) {
-                double *dst = part + pl->poff[c] + split * ncomp * na;
-#pragma unroll
-                for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + qw] = aw[cc];
-            }
-            continue;
-        }
-        // this lane's active row
-        const int64_t q0 = tile_i * BLOCK + threadIdx.x;
-        const int64_t q = q0 < na ? q0 : na - 1;
-        const int32_t *al = act + pl->aoff[c];
-        typename Pol::I ip[1];
-        int64_t iidx[1];
-        double acc[1][13];
-        {
-            const int64_t ia = al[q];
-            iidx[0] = (ia >= base && ia < base + nn) ? ia : base;
-            ip[0] = Pol::load(rec[iidx[0]]);
-#pragma unroll
-            for (int cc = 0; cc < 13; ++cc) acc[0][cc] = 0.0;
-        }
-        hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
-        const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
-        lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
-        if (q0 < na) {
-            double *dst = part + pl->poff[c] + split * ncomp * na;
-#pragma unroll
-            for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + q0] = acc[0][cc];
         }
     }
 }
@@ -450,9 +590,10 @@ k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *_
     }
 }
 
+// Work queues back to empty (a second force pass on the same plan).
 __global__ void k_b_requeue(BatchPlan *__restrict__ pl)
 {
-    if (threadIdx.x == 0) pl->queue = 0;
+    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 8] = 0;
 }
 
 unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -465,14 +606,16 @@ constexpr unsigned kStrideGrid = 2048;
 template <class Pol, int P>
 hipError_t force_p(const BatchLaunch &L, const void *rec, hipStream_t s)
 {
+    const auto *r = static_cast<const typename Pol::Rec *>(rec);
     if (L.itile == 64)
-        hipLaunchKernelGGL((k_b_force<Pol, P, 64, 64>), dim3(L.force_grid), dim3(64), 0, s,
-                           static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
-                           L.n_hard, 3 * (P / 2), L.part);
+        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 64>), dim3(L.force_grid), dim3(64), 0, s, r, L.off, L.ord,
+                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
+    else if (L.itile == 128)
+        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 128>), dim3(L.force_grid), dim3(64), 0, s, r, L.off, L.ord,
+                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
     else
-        hipLaunchKernelGGL((k_b_force<Pol, P, 256, 128>), dim3(L.force_grid), dim3(256), 0, s,
-                           static_cast<const typename Pol::Rec *>(rec), L.off, L.ord, L.nc, L.act, L.plan, L.eps2,
-                           L.n_hard, 3 * (P / 2), L.part);
+        hipLaunchKernelGGL((k_b_force<Pol, P, 256, 128, 256>), dim3(L.force_grid), dim3(256), 0, s, r, L.off, L.ord,
+                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
     return hipGetLastError();
 }
 
@@ -506,8 +649,9 @@ int resident_p(int itile, int device)
 {
     int per_cu = 0, cus = 0;
     const hipError_t e = itile == 64
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 64, 64>, 64, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 256, 128>, 256, 0);
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 64, kBTile, 64>, 64, 0)
+        : itile == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 64, kBTile, 128>, 64, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_force<Pol, P, 256, 128, 256>, 256, 0);
     if (e != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
     return per_cu * cus;

@@ -63,7 +63,7 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.act = take(n * sizeof(int32_t));
     // split partials: the plan keeps sum_c splits_c * active_c <= i_tile *
     // items + n; 12 components (the order-8 initialisation passes)
-    L.part = take(12 * (size_t(nb::kBatchMaxItems) * nb::kBatchITileMax + n) * sizeof(double));
+    L.part = take(12 * (size_t(nb::kBatchMaxRows) + n) * sizeof(double));
     L.force = take(12 * n * sizeof(double));
     L.rec = take(n * size_t(std::max(nb::record_bytes(c.order, c.precision), nb::record_bytes(8, NBODY_FP64))));
     L.energy = take(2 * size_t(sum_energy_blocks(off)) * sizeof(double));
@@ -228,7 +228,6 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.per_wg = 4;
     L.itile = 64;
     nb::BatchPlan hp{};
-    hp.queue = 0;
     hp.t_end = INT64_MAX;
     hp.n_live = 0;
     hp.nact = at<int64_t>(b, lay.nact);
@@ -243,7 +242,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
         b->force_grid_req = 0;
         L.force_grid = nb::batch_force_resident(cfg->order, cfg->precision, L.itile, b->device);
         if (L.force_grid <= 0) e = hipErrorInvalidDeviceFunction;
-        L.k_items = std::min(L.force_grid * L.per_wg, nb::kBatchMaxItems);
+        L.k_items = int(std::min<int64_t>(int64_t(L.force_grid) * L.per_wg, nb::kBatchMaxRows / L.itile));
     }
     if (e == hipSuccess) e = hipMemcpyAsync(L.plan, &hp, sizeof(hp), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int64_t *>(L.off), b->off.data(), b->off.size() * sizeof(int64_t),
@@ -301,7 +300,6 @@ nbody_status nbody_batch_set_end(nbody_batch *b, int64_t t_end_tick)
 {
     if (!b) return fail(NBODY_E_INVALID, "batch is NULL");
     if (t_end_tick < 0) return fail(NBODY_E_INVALID, "t_end_tick must be >= 0");
-    static_assert(offsetof(nb::BatchPlan, t_end) == 8, "plan layout");
     // the value must outlive the asynchronous copy: copy, then synchronise
     const int64_t v = t_end_tick;
     NB_HIP(hipMemcpyAsync(reinterpret_cast<char *>(b->L.plan) + offsetof(nb::BatchPlan, t_end), &v, sizeof(v),
@@ -448,14 +446,15 @@ nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t 
     if (force_grid < 0 || force_grid > (1 << 20)) return fail(NBODY_E_INVALID, "force_grid must be in [0, 2^20]");
     if (per_wg < 0 || per_wg > nb::kBatchMaxPerWG)
         return fail(NBODY_E_INVALID, "items_per_wg must be in [0, %d]", nb::kBatchMaxPerWG);
-    if (i_tile != 0 && i_tile != 64 && i_tile != 256) return fail(NBODY_E_INVALID, "i_tile must be 0, 64 or 256");
+    if (i_tile != 0 && i_tile != 64 && i_tile != 128 && i_tile != 256)
+        return fail(NBODY_E_INVALID, "i_tile must be 0, 64, 128 or 256");
     nb::BatchLaunch &L = b->L;
     L.itile = i_tile > 0 ? i_tile : 64;
     L.per_wg = per_wg > 0 ? per_wg : 4;
     b->force_grid_req = force_grid;
     L.force_grid = force_grid > 0 ? force_grid : nb::batch_force_resident(b->cfg.order, b->cfg.precision, L.itile, b->device);
     if (L.force_grid <= 0) return fail(NBODY_E_HIP, "occupancy query of the batched force kernel failed");
-    L.k_items = int(std::min<int64_t>(int64_t(L.force_grid) * L.per_wg, nb::kBatchMaxItems));
+    L.k_items = int(std::min<int64_t>(int64_t(L.force_grid) * L.per_wg, nb::kBatchMaxRows / L.itile));
     return NBODY_OK;
 }
 
@@ -481,7 +480,7 @@ nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *st, int32_t steps
         (void)hipEventDestroy(e0);
         return fail(NBODY_E_HIP, "hipEventCreate failed");
     }
-    const int itiles[2] = {64, 256};
+    const int itiles[3] = {64, 128, 256};
     const int targets[5] = {1, 2, 4, 8, 16};
     double best = -1.0;
     int best_i = 64, best_t = 16;

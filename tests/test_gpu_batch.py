@@ -126,14 +126,17 @@ def test_batch_force_all_active(order, precision):
             assert st["rms"] <= LOW_TOL[key], (key, st)
 
 
-@pytest.mark.parametrize("shape", [(64, 4), (256, 4), (64, 16), (256, 1), (64, 1)])
+@pytest.mark.parametrize("shape,precision", [((64, 4), "fp64"), ((256, 4), "fp64"), ((64, 16), "fp64"),
+                                             ((256, 1), "fp64"), ((64, 1), "fp64"), ((128, 4), "fp64"),
+                                             ((64, 32), "fp64"), ((64, 4), "mixed"), ((128, 32), "mixed")])
 @pytest.mark.parametrize("order", [4, 6, 8])
-def test_batch_force_block_steps(order, shape):
+def test_batch_force_block_steps(order, shape, precision):
     """Individual block steps: every cluster at its own time with its own
     (small) active set, j-ranges split into items of equal cost; i-tiles of
-    64 and 256 rows, 1 to 16 work items aimed for per workgroup."""
+    64, 128 and 256 rows (a tile's last active rows spread over lane groups
+    of 2 to 64 lanes), 1 to 32 work items aimed for per workgroup."""
     models = _clusters(920)
-    B = _batch(models, order, "fp64")
+    B = _batch(models, order, precision)
     B.set_launch(0, shape[1], shape[0])
     assert B.get_launch()[1:] == (shape[1], shape[0])
     B.init()
@@ -149,8 +152,11 @@ def test_batch_force_block_steps(order, shape):
     say("batch block steps order %d: %d active rows in 6 steps" % (order, n_rows))
     for key in KEYS[: order // 2]:
         st = err_stats(np.concatenate(errs[key]))
-        say("batch force blocks order %d %s rms %.2e max %.2e" % (order, key, st["rms"], st["max"]))
-        assert st["rms"] <= 1e-12 and st["max"] <= 1e-9, (key, st)
+        say("batch force blocks order %d %s %s rms %.2e max %.2e" % (order, precision, key, st["rms"], st["max"]))
+        if precision == "fp64":
+            assert st["rms"] <= 1e-12 and st["max"] <= 1e-9, (key, st)
+        else:
+            assert st["rms"] <= LOW_TOL[key] and st["max"] <= 10 * LOW_TOL[key], (key, st)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -287,8 +293,8 @@ def test_batch_autotune_keeps_parity():
     B.autotune(1)
     grid, per_wg, itile = B.get_launch()
     say("autotuned batch shape: grid %d items per workgroup %d i_tile %d" % (grid, per_wg, itile))
-    assert grid > 0 and per_wg in (1, 2, 4, 8, 16) and itile in (64, 256)
-    assert B.stats().steps == 20
+    assert grid > 0 and per_wg in (1, 2, 4, 8, 16) and itile in (64, 128, 256)
+    assert B.stats().steps == 15 * 2   # 15 shapes, one untimed and one timed step each
     ocfg = _ocfg(B)
     errs = {k: [] for k in KEYS}
     for step in range(3):
