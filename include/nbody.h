@@ -390,7 +390,7 @@ nbody_status nbody_batch_get_stats(nbody_batch *b, nbody_stats *out);
 
 /* Persistent force launch: force_grid workgroups (0 = as many as fit on the
  * device at once), items_per_wg work items aimed for per workgroup (1..32,
- * 0 = 4: each step's padded work is cut into about force_grid * items_per_wg
+ * 0 = 8: each step's padded work is cut into about force_grid * items_per_wg
  * items of equal cost, at most 2^22 / i_tile, by splitting each cluster's
  * j-range into pieces of at least 128) and i_tile active rows per work item
  * (64, 128 or 256, 0 = 64).  Applies to later steps and captures (a captured graph keeps
@@ -403,7 +403,7 @@ nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t 
 nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3]);
 
 /* Autotuner: times `steps` batched steps (after one untimed step) for each
- * i_tile in {64, 128, 256} and items_per_wg in {1, 2, 4, 8, 16} with HIP events,
+ * i_tile in {64, 128, 256} and items_per_wg in {2, 4, 8, 16, 32} with HIP events,
  * and keeps the shape with the most pair interactions per second.  The
  * steps are real: the clusters advance by 15 * (steps + 1) batched steps
  * (fewer where they reach t_end).  Drops a captured graph (capture again). */

@@ -12,6 +12,19 @@ constexpr int kBatchMaxPerWG = 32;     // most items aimed for per persistent wo
 constexpr int kBatchSchedBlock = 1024;  // particles per scheduling block
 constexpr int kXcds = 8;                // XCDs of the device: work queues of the persistent force kernel
 
+// The work of the cluster of one rank (plan order) in a step, written by
+// the plan for the persistent force kernel: one 64-byte load per work item.
+struct BatchRank {
+    int64_t i0, i1;   // its work items [i0, i1)
+    int64_t base;     // first particle
+    int64_t jc;       // j-range per split
+    int64_t poff;     // offset of its split partials (doubles)
+    int64_t aoff;     // offset of its active list
+    int32_t nn, na;   // particles, active rows
+    int32_t sp, c;    // j-splits, cluster index
+};
+static_assert(sizeof(BatchRank) == 64, "one 64-byte record per rank");
+
 // Written by the plan kernel of every batched step and read by the kernels
 // after it.  Arrays sized n_clusters + 1 (the last entry of a scanned array
 // holds its total).
@@ -26,9 +39,10 @@ struct BatchPlan {
     int64_t *jchunk;            // [nc]   j-range per split
     int32_t *split;             // [nc]   j-splits per cluster
     int64_t *tcur;              // [nc]   time of the cluster's last completed step
+    BatchRank *rank;            // [nc]   work of each cluster rank
     // items taken from each XCD's eighth of the step's items (one 64-byte
     // line per counter); reset by the plan
-    unsigned long long queue[kXcds * 8];
+    unsigned queue[kXcds * 16];
 };
 
 struct BatchCounters {
@@ -45,6 +59,8 @@ struct BatchCounters {
 struct BatchLaunch {
     int nc;                     // clusters
     int nb;                     // scheduling blocks per cluster (largest cluster / 1024, rounded up)
+    int nblk;                   // scheduling blocks of all clusters
+    const int32_t *blk;         // [nblk][2] (cluster, block) of each
     int64_t n;                  // particles in all clusters
     const int64_t *off;         // [nc+1] cluster offsets
     const int32_t *ord;         // [nc]   clusters by decreasing size

@@ -37,14 +37,15 @@ __device__ __forceinline__ int64_t b_next(const int64_t *t_tick, const int32_t *
     return t_tick[i] + (int64_t(1) << (kLevelMax - level[i]));
 }
 
-// Block b of cluster c covers [off[c] + b*kBBlock, min(off[c] + (b+1)*kBBlock, off[c+1])).
+// Block b of cluster c covers [off[c] + b*kBBlock, min(off[c] + (b+1)*kBBlock, off[c+1])); the
+// launch has one workgroup per such block, (c, b) = blk[2x], blk[2x + 1].
 // Also clears the cluster's active count, which k_b_count accumulates.
 __global__ void __launch_bounds__(kBThreads)
 k_b_min(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-        int nb, int64_t *__restrict__ bmin, BatchPlan *__restrict__ pl)
+        int nb, const int32_t *__restrict__ blk, int64_t *__restrict__ bmin, BatchPlan *__restrict__ pl)
 {
     __shared__ int64_t sm[kBThreads];
-    const int c = blockIdx.y, b = blockIdx.x;
+    const int c = blk[2 * blockIdx.x], b = blk[2 * blockIdx.x + 1];
     if (b == 0 && threadIdx.x == 0) pl->nact[c] = 0;
     const int64_t lo = off[c] + int64_t(b) * kBBlock, hi = off[c + 1];
     int64_t mn = INT64_MAX;
@@ -70,14 +71,15 @@ k_b_min(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, con
 // (initialisation).
 __global__ void __launch_bounds__(kBThreads)
 k_b_count(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-          int nb, const int64_t *__restrict__ bmin, int all_active, BatchPlan *__restrict__ pl,
-          int64_t *__restrict__ tnext, int32_t *__restrict__ bcnt)
+          int nb, const int32_t *__restrict__ blk, const int64_t *__restrict__ bmin, int all_active,
+          BatchPlan *__restrict__ pl, int64_t *__restrict__ tnext, int32_t *__restrict__ bcnt)
 {
     __shared__ int64_t sm[kBThreads];
     __shared__ int cnt[kBThreads];
-    const int c = blockIdx.y, b = blockIdx.x;
+    const int c = blk[2 * blockIdx.x], b = blk[2 * blockIdx.x + 1];
+    const int nbc = int((off[c + 1] - off[c] + kBBlock - 1) / kBBlock);   // the cluster's blocks
     int64_t mn = INT64_MAX;
-    for (int k = threadIdx.x; k < nb; k += kBThreads) {
+    for (int k = threadIdx.x; k < nbc; k += kBThreads) {
         const int64_t v = bmin[int64_t(c) * nb + k];
         mn = v < mn ? v : mn;
     }
@@ -194,7 +196,22 @@ k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ or
     __syncthreads();
     block_scan(pl->ioff, nc, sh);
     block_scan(pl->poff, nc, sh);
-    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 8] = 0;
+    for (int r = threadIdx.x; r < nc; r += kBThreads) {
+        const int c = ord[r];
+        BatchRank d;
+        d.i0 = pl->ioff[r];
+        d.i1 = pl->ioff[r + 1];
+        d.base = off[c];
+        d.jc = pl->jchunk[c];
+        d.poff = pl->poff[c];
+        d.aoff = pl->aoff[c];
+        d.nn = int32_t(off[c + 1] - off[c]);
+        d.na = int32_t(pl->nact[c]);
+        d.sp = pl->split[c];
+        d.c = c;
+        pl->rank[r] = d;
+    }
+    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 16] = 0u;
     if (threadIdx.x == 0) {
         pl->n_live = live;
         ctr->interactions += inter;
@@ -207,13 +224,14 @@ k_b_plan(int nc, const int64_t *__restrict__ off, const int32_t *__restrict__ or
 // cluster's earlier blocks, at aoff[c] + sum of bcnt[c][0 .. b).
 __global__ void __launch_bounds__(kBThreads)
 k_b_compact(const int64_t *__restrict__ off, const int64_t *__restrict__ t_tick, const int32_t *__restrict__ level,
-            int nb, const int64_t *__restrict__ tnext, const int32_t *__restrict__ bcnt, int all_active,
-            const BatchPlan *__restrict__ pl, int32_t *__restrict__ act)
+            int nb, const int32_t *__restrict__ blk, const int64_t *__restrict__ tnext,
+            const int32_t *__restrict__ bcnt, int all_active, const BatchPlan *__restrict__ pl,
+            int32_t *__restrict__ act)
 {
     __shared__ int s[kBThreads];
     __shared__ int64_t sb[kBThreads];
     constexpr int PER = kBBlock / kBThreads;
-    const int c = blockIdx.y, b = blockIdx.x;
+    const int c = blk[2 * blockIdx.x], b = blk[2 * blockIdx.x + 1];
     int64_t before = 0;
     for (int k = threadIdx.x; k < b; k += kBThreads) before += bcnt[int64_t(c) * nb + k];
     const int64_t block_off = pl->aoff[c] + block_sum(before, sb);
@@ -448,123 +466,154 @@ __device__ __forceinline__ void b_item_rows(int rows, const typename Pol::Rec *_
 template <class Pol, int P, int BLOCK>
 constexpr int b_waves() { return (BLOCK == 64 && sizeof(typename Pol::Part) == 4 && P <= 6) ? 3 : 1; }
 
+// One work item: the i-tile and j-split `local` of the cluster described by d.
+template <class Pol, int P, int BLOCK, int TILE, int ROWS>
+__device__ __forceinline__ void b_run(const BatchRank &d, int64_t local, const typename Pol::Rec *__restrict__ rec,
+                                      const int32_t *__restrict__ act, typename Pol::ET e2, int64_t n_hard, int ncomp,
+                                      double *__restrict__ part, typename Pol::Rec (*tile)[TILE])
+{
+    const uint32_t lq = uint32_t(local), sp = uint32_t(d.sp);
+    const int64_t tile_i = lq / sp, split = lq % sp;
+    const int64_t na = d.na, base = d.base, nn = d.nn, jc = d.jc;
+    const int64_t j0 = base + split * jc;
+    const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
+    const int64_t nh = n_hard < nn ? n_hard : nn;
+    double *dst = part + d.poff + split * ncomp * na;
+    const int32_t *al = act + d.aoff;
+    if constexpr (BLOCK == 64) {
+        const int64_t row0 = tile_i * ROWS;
+        const int64_t rows = na - row0 < ROWS ? na - row0 : ROWS;
+        b_item_rows<Pol, P, TILE, ROWS>(int(rows), rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+    } else {
+        // this lane's active row
+        const int64_t q0 = tile_i * BLOCK + threadIdx.x;
+        const int64_t q = q0 < na ? q0 : na - 1;
+        typename Pol::I ip[1];
+        int64_t iidx[1];
+        double acc[1][13];
+        const int64_t ia = al[q];
+        iidx[0] = (ia >= base && ia < base + nn) ? ia : base;
+        ip[0] = Pol::load(rec[iidx[0]]);
+#pragma unroll
+        for (int cc = 0; cc < 13; ++cc) acc[0][cc] = 0.0;
+        hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
+        const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
+        lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
+        if (q0 < na) {
+#pragma unroll
+            for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + q0] = acc[0][cc];
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t wave_uniform(uint32_t v) { return int64_t(uint32_t(__builtin_amdgcn_readfirstlane(v))); }
+
 template <class Pol, int P, int BLOCK, int TILE, int ROWS>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(b_waves<Pol, P, BLOCK>())))
-k_b_force(const typename Pol::Rec *__restrict__ rec, const int64_t *__restrict__ off, const int32_t *__restrict__ ord,
-          int nc, const int32_t *__restrict__ act, BatchPlan *__restrict__ pl, double eps2, int64_t n_hard,
-          int ncomp, double *__restrict__ part)
+k_b_force(const typename Pol::Rec *__restrict__ rec, int nc, const int32_t *__restrict__ act,
+          BatchPlan *__restrict__ pl, double eps2, int64_t n_hard, int ncomp, double *__restrict__ part)
 {
     using Rec = typename Pol::Rec;
     using ET = typename Pol::ET;
     __shared__ Rec tile[2][TILE];
-    __shared__ int64_t s_take;
+    __shared__ uint32_t s_take;
     const ET e2 = ET(eps2);
-    const int64_t total = pl->ioff[nc];
+    const BatchRank *__restrict__ rk = pl->rank;
+    const int64_t total = rk[nc - 1].i1;
     const int x0 = int(blockIdx.x) % kXcds;
+    const int64_t ahead = 2 * ((int64_t(gridDim.x) + kXcds - 1) / kXcds);   // two items per workgroup of an XCD
     for (int v = 0; v < kXcds; ++v) {
         const int xr = (x0 + v) % kXcds;
         const int64_t r0 = total * xr / kXcds, len = total * (xr + 1) / kXcds - r0;
-        unsigned long long *q = &pl->queue[xr * 8];
-        for (;;) {
-            __syncthreads();   // the previous item's tiles and s_take are no longer read
-            if (threadIdx.x == 0) {
-                // an exhausted range is seen with a load, without adding to its counter
-                const unsigned long long seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_take = seen >= (unsigned long long)len ? len : int64_t(atomicAdd(q, 1ull));
-            }
-            __syncthreads();
-            // the same value in every lane: made scalar, so that everything
-            // derived from it (cluster, ranges, loop bounds) stays in SGPRs
-            const uint64_t tv = uint64_t(s_take);
-            const uint32_t th = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(tv >> 32)));
-            const uint32_t tl = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(tv)));
-            const int64_t take = int64_t((uint64_t(th) << 32) | tl);
-            if (take >= len) break;
-            const int64_t item = r0 + take;
-            // rank of the item's cluster: ioff[lo] <= item < ioff[lo + 1]
-            int lo = 0, hi = nc;
+        uint32_t *q = &pl->queue[xr * 16];
+        // the first item of this range; an exhausted range is seen with a
+        // load, without adding to its counter
+        __syncthreads();   // the previous item's tiles and s_take are no longer read
+        if (threadIdx.x == 0) {
+            const uint32_t seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_take = seen >= uint32_t(len) ? uint32_t(len) : atomicAdd(q, 1u);
+        }
+        __syncthreads();
+        int64_t take = wave_uniform(s_take);   // scalar: the cluster, ranges and loop bounds stay in SGPRs
+        if (take >= len) continue;
+        // rank of the item's cluster: rk[lo].i0 <= item < rk[lo].i1; the
+        // items a workgroup takes from one range only increase
+        int lo = 0;
+        {
+            int hi = nc;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) / 2;
-                if (pl->ioff[mid] <= item) lo = mid; else hi = mid;
+                if (rk[mid].i0 <= r0 + take) lo = mid; else hi = mid;
             }
-            const int c = ord[lo];
-            const int64_t local = item - pl->ioff[lo];
-            const int sp = pl->split[c];
-            const int64_t tile_i = local / sp, split = local % sp;
-            const int64_t na = pl->nact[c], base = off[c], nn = off[c + 1] - base;
-            const int64_t jc = pl->jchunk[c];
-            const int64_t j0 = base + split * jc;
-            const int64_t j1 = (split + 1) * jc < nn ? base + (split + 1) * jc : base + nn;
-            const int64_t nh = n_hard < nn ? n_hard : nn;
-            double *dst = part + pl->poff[c] + split * ncomp * na;
-            const int32_t *al = act + pl->aoff[c];
-            if constexpr (BLOCK == 64) {
-                const int64_t row0 = tile_i * ROWS;
-                const int64_t rows = na - row0 < ROWS ? na - row0 : ROWS;
-                b_item_rows<Pol, P, TILE, ROWS>(int(rows), rec, al, na, row0, base, nn, nh, j0, j1, e2, tile, dst);
+        }
+        for (;;) {
+            const int64_t item = r0 + take;
+            while (rk[lo].i1 <= item) ++lo;
+            const BatchRank d = rk[lo];
+            // one wave, far from the range's end: the next item is claimed
+            // now and its number read after this one, so the atomic's latency
+            // is not waited for (near the end a claimed item would wait for
+            // this one while other workgroups idle)
+            const bool early = BLOCK == 64 && take + ahead < len;
+            uint32_t nxt = 0u;
+            if (early && threadIdx.x == 0) nxt = atomicAdd(q, 1u);
+            b_run<Pol, P, BLOCK, TILE, ROWS>(d, item - d.i0, rec, act, e2, n_hard, ncomp, part, tile);
+            if (early) {
+                take = wave_uniform(nxt);
             } else {
-                // this lane's active row
-                const int64_t q0 = tile_i * BLOCK + threadIdx.x;
-                const int64_t q = q0 < na ? q0 : na - 1;
-                typename Pol::I ip[1];
-                int64_t iidx[1];
-                double acc[1][13];
-                {
-                    const int64_t ia = al[q];
-                    iidx[0] = (ia >= base && ia < base + nn) ? ia : base;
-                    ip[0] = Pol::load(rec[iidx[0]]);
-#pragma unroll
-                    for (int cc = 0; cc < 13; ++cc) acc[0][cc] = 0.0;
-                }
-                hard_pairs<Pol, 1>(rec, j0, (j1 < base + nh) ? j1 : base + nh, base, nh, e2, ip, iidx, acc);
-                const int64_t js0 = (j0 > base + nh) ? j0 : base + nh;
-                lds_tiles<Pol, 1, BLOCK, 2, TILE>(rec, js0, j1, e2, ip, iidx, tile, acc);
-                if (q0 < na) {
-#pragma unroll
-                    for (int cc = 0; cc < 3 * (P / 2); ++cc) dst[int64_t(cc) * na + q0] = acc[0][cc];
-                }
+                __syncthreads();   // the item's tiles and s_take are no longer read
+                if (threadIdx.x == 0) s_take = atomicAdd(q, 1u);
+                __syncthreads();
+                take = wave_uniform(s_take);
             }
+            if (take >= len) break;
         }
     }
 }
 
 // Row r of the concatenated active list: sum of its cluster's split partials
-// into outputs [3][stride] (acc, jerk, snap, crackle).  Each output value is
-// owned by a group of kRedLanes consecutive lanes: lane l adds splits l,
-// l + kRedLanes, ... in order, then the group folds its sums with a fixed
-// butterfly (the order depends only on the cluster's split count).
+// into outputs [3][stride] (acc, jerk, snap, crackle).  A group of kRedLanes
+// consecutive lanes owns a row (its cluster found through the row's particle):
+// for every component, lane l adds splits l, l + kRedLanes, ... in order,
+// then the group folds its sums with a fixed butterfly (the order depends
+// only on the cluster's split count).
 constexpr int kRedLanes = 16;
 
 template <int P>
 __global__ void __launch_bounds__(256)
-k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, int ncomp, const double *__restrict__ part,
-           double *__restrict__ o0, double *__restrict__ o1, double *__restrict__ o2, double *__restrict__ o3,
-           int64_t stride)
+k_b_reduce(int nc, int64_t n, const BatchPlan *__restrict__ pl, const int32_t *__restrict__ act,
+           const int32_t *__restrict__ cid, int ncomp, const double *__restrict__ part, double *__restrict__ o0,
+           double *__restrict__ o1, double *__restrict__ o2, double *__restrict__ o3, int64_t stride)
 {
     constexpr int NV = 3 * (P / 2);
     const int64_t total = pl->aoff[nc];
     const int l = int(threadIdx.x) % kRedLanes;
     const int64_t groups = int64_t(gridDim.x) * blockDim.x / kRedLanes;
-    // the lanes of a group share g, so they run the same iterations and their
+    double *outs[4] = {o0, o1, o2, o3};
+    // the lanes of a group share r, so they run the same iterations and their
     // exchanges (within the group) always find their partners active
-    for (int64_t g = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kRedLanes; g < total * NV; g += groups) {
-        const int cc = int(g / total);
-        const int64_t r = g - int64_t(cc) * total;
-        int lo = 0, hi = nc;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) / 2;
-            if (pl->aoff[mid] <= r) lo = mid; else hi = mid;
-        }
-        const int64_t na = pl->nact[lo], q = r - pl->aoff[lo];
-        const double *src = part + pl->poff[lo];
-        double s = 0.0;
-        for (int sp = l; sp < pl->split[lo]; sp += kRedLanes) s += src[(int64_t(sp) * ncomp + cc) * na + q];
+    for (int64_t r = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kRedLanes; r < total; r += groups) {
+        const int64_t i = act[r];
+        const int c = (i >= 0 && i < n) ? cid[i] : 0;
+        const int64_t na = pl->nact[c], q = r - pl->aoff[c];
+        if (q < 0 || q >= na) continue;   // never for a consistent plan; the whole group skips together
+        const double *src = part + pl->poff[c];
+        const int sp = pl->split[c];
+        double s[NV];
 #pragma unroll
-        for (int m = kRedLanes / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-        if (l == 0) {
-            double *outs[4] = {o0, o1, o2, o3};
+        for (int cc = 0; cc < NV; ++cc) s[cc] = 0.0;
+        for (int k = l; k < sp; k += kRedLanes)
+#pragma unroll
+            for (int cc = 0; cc < NV; ++cc) s[cc] += src[(int64_t(k) * ncomp + cc) * na + q];
+#pragma unroll
+        for (int m = kRedLanes / 2; m > 0; m >>= 1)
+#pragma unroll
+            for (int cc = 0; cc < NV; ++cc) s[cc] += __shfl_xor(s[cc], m, 64);
+        // lane l of the group stores component l
+#pragma unroll
+        for (int cc = 0; cc < NV; ++cc) {
             double *o = outs[cc / 3];
-            if (o) o[(cc % 3) * stride + r] = s;
+            if (l == cc % kRedLanes && o) o[(cc % 3) * stride + r] = s[cc];
         }
     }
 }
@@ -593,7 +642,7 @@ k_b_correct(int64_t n, int nc, const int32_t *__restrict__ act, const int32_t *_
 // Work queues back to empty (a second force pass on the same plan).
 __global__ void k_b_requeue(BatchPlan *__restrict__ pl)
 {
-    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 8] = 0;
+    if (threadIdx.x < kXcds) pl->queue[threadIdx.x * 16] = 0u;
 }
 
 unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -608,14 +657,14 @@ hipError_t force_p(const BatchLaunch &L, const void *rec, hipStream_t s)
 {
     const auto *r = static_cast<const typename Pol::Rec *>(rec);
     if (L.itile == 64)
-        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 64>), dim3(L.force_grid), dim3(64), 0, s, r, L.off, L.ord,
-                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
+        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 64>), dim3(L.force_grid), dim3(64), 0, s, r, L.nc, L.act,
+                           L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
     else if (L.itile == 128)
-        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 128>), dim3(L.force_grid), dim3(64), 0, s, r, L.off, L.ord,
-                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
+        hipLaunchKernelGGL((k_b_force<Pol, P, 64, kBTile, 128>), dim3(L.force_grid), dim3(64), 0, s, r, L.nc, L.act,
+                           L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
     else
-        hipLaunchKernelGGL((k_b_force<Pol, P, 256, 128, 256>), dim3(L.force_grid), dim3(256), 0, s, r, L.off, L.ord,
-                           L.nc, L.act, L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
+        hipLaunchKernelGGL((k_b_force<Pol, P, 256, 128, 256>), dim3(L.force_grid), dim3(256), 0, s, r, L.nc, L.act,
+                           L.plan, L.eps2, L.n_hard, 3 * (P / 2), L.part);
     return hipGetLastError();
 }
 
@@ -630,9 +679,9 @@ hipError_t force_prec(int precision, const BatchLaunch &L, const void *rec, hipS
 template <int P>
 hipError_t reduce_p(const BatchLaunch &L, double *o0, double *o1, double *o2, double *o3, hipStream_t s)
 {
-    const unsigned g = nblk(L.n * 3 * (P / 2) * kRedLanes, 256);
+    const unsigned g = nblk(L.n * kRedLanes, 256);
     hipLaunchKernelGGL((k_b_reduce<P>), dim3(g < kStrideGrid ? g : kStrideGrid), dim3(256), 0, s, L.nc, L.n, L.plan,
-                       3 * (P / 2), L.part, o0, o1, o2, o3, L.n);
+                       L.act, L.cid, 3 * (P / 2), L.part, o0, o1, o2, o3, L.n);
     return hipGetLastError();
 }
 
@@ -680,14 +729,14 @@ hipError_t batch_cid(const BatchLaunch &L, hipStream_t s)
 
 hipError_t batch_schedule(const BatchLaunch &L, const nbody_state &st, int all_active, int order, hipStream_t s)
 {
-    const dim3 g(unsigned(L.nb), unsigned(L.nc), 1u);
-    hipLaunchKernelGGL(k_b_min, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, L.plan);
-    hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.bmin, all_active,
-                       L.plan, L.tnext, L.bcnt);
+    const dim3 g(unsigned(L.nblk));   // the clusters' scheduling blocks, flat
+    hipLaunchKernelGGL(k_b_min, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.blk, L.bmin, L.plan);
+    hipLaunchKernelGGL(k_b_count, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.blk, L.bmin,
+                       all_active, L.plan, L.tnext, L.bcnt);
     hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kBThreads), 0, s, L.nc, L.off, L.ord, L.tnext, L.plan,
                        3 * (order / 2), L.k_items, L.itile, L.ctr);
-    hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.tnext, L.bcnt,
-                       all_active, L.plan, L.act);
+    hipLaunchKernelGGL(k_b_compact, g, dim3(kBThreads), 0, s, L.off, st.t_tick, st.level, L.nb, L.blk, L.tnext,
+                       L.bcnt, all_active, L.plan, L.act);
     return hipGetLastError();
 }
 

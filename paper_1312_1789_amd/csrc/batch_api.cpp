@@ -17,7 +17,7 @@ using nb::fail;
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BatchLayout {
-    size_t off, ord, cid, tnext, bmin, bcnt, plan, nact, aoff, ioff, poff, jchunk, split, tcur, ctr, act,
+    size_t off, ord, cid, tnext, bmin, bcnt, blk, plan, nact, aoff, ioff, poff, jchunk, split, tcur, rank, ctr, act,
         part, force, rec, energy, total;
 };
 
@@ -26,6 +26,14 @@ int64_t max_cluster(const std::vector<int64_t> &off)
     int64_t m = 0;
     for (size_t c = 0; c + 1 < off.size(); ++c) m = std::max(m, off[c + 1] - off[c]);
     return m;
+}
+
+// Scheduling blocks of all clusters (each cluster in blocks of kBatchSchedBlock).
+int64_t sched_blocks(const std::vector<int64_t> &off)
+{
+    int64_t s = 0;
+    for (size_t c = 0; c + 1 < off.size(); ++c) s += (off[c + 1] - off[c] + nb::kBatchSchedBlock - 1) / nb::kBatchSchedBlock;
+    return s;
 }
 
 int64_t sum_energy_blocks(const std::vector<int64_t> &off)
@@ -51,6 +59,7 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.tnext = take(nc * sizeof(int64_t));
     L.bmin = take(cells * sizeof(int64_t));
     L.bcnt = take(cells * sizeof(int32_t));
+    L.blk = take(2 * size_t(sched_blocks(off)) * sizeof(int32_t));
     L.plan = take(sizeof(nb::BatchPlan));
     L.nact = take(nc * sizeof(int64_t));
     L.aoff = take((nc + 1) * sizeof(int64_t));
@@ -59,6 +68,7 @@ BatchLayout make_batch_layout(const nbody_config &c, const std::vector<int64_t> 
     L.jchunk = take(nc * sizeof(int64_t));
     L.split = take(nc * sizeof(int32_t));
     L.tcur = take(nc * sizeof(int64_t));
+    L.rank = take(nc * sizeof(nb::BatchRank));
     L.ctr = take(sizeof(nb::BatchCounters));
     L.act = take(n * sizeof(int32_t));
     // split partials: the plan keeps sum_c splits_c * active_c <= i_tile *
@@ -85,6 +95,8 @@ nbody_status check_batch(const nbody_config *cfg, int32_t nc, const int64_t *off
     for (int c = 0; c < nc; ++c) {
         const int64_t sz = off[c + 1] - off[c];
         if (sz < 2) return fail(NBODY_E_INVALID, "cluster %d has %lld particles (need >= 2)", c, (long long)sz);
+        if (sz >= (int64_t(1) << 31))
+            return fail(NBODY_E_UNSUPPORTED, "cluster %d has %lld particles (at most 2^31 - 1)", c, (long long)sz);
         smallest = std::min(smallest, sz);
     }
     if (off[nc] != cfg->n) return fail(NBODY_E_INVALID, "off[n_clusters] = %lld must equal n = %lld",
@@ -108,6 +120,7 @@ struct nbody_batch {
     int nc;
     std::vector<int64_t> off;
     std::vector<int32_t> ord;
+    std::vector<int32_t> blk;   // (cluster, block) of every scheduling block
     hipStream_t stream;
     char *ws;
     BatchLayout lay;
@@ -218,6 +231,15 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.tnext = at<int64_t>(b, lay.tnext);
     L.bmin = at<int64_t>(b, lay.bmin);
     L.bcnt = at<int32_t>(b, lay.bcnt);
+    for (int c = 0; c < n_clusters; ++c) {
+        const int64_t nbc = (o[size_t(c) + 1] - o[size_t(c)] + nb::kBatchSchedBlock - 1) / nb::kBatchSchedBlock;
+        for (int64_t k = 0; k < nbc; ++k) {
+            b->blk.push_back(c);
+            b->blk.push_back(int32_t(k));
+        }
+    }
+    L.nblk = int(b->blk.size() / 2);
+    L.blk = at<int32_t>(b, lay.blk);
     L.plan = at<nb::BatchPlan>(b, lay.plan);
     L.ctr = at<nb::BatchCounters>(b, lay.ctr);
     L.act = at<int32_t>(b, lay.act);
@@ -225,7 +247,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     L.force = at<double>(b, lay.force);
     L.eps2 = cfg->eps2;
     L.n_hard = cfg->eps2 == 0.0 ? (int64_t(1) << 40) : cfg->n_hard;
-    L.per_wg = 4;
+    L.per_wg = 8;
     L.itile = 64;
     nb::BatchPlan hp{};
     hp.t_end = INT64_MAX;
@@ -237,6 +259,7 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     hp.jchunk = at<int64_t>(b, lay.jchunk);
     hp.split = at<int32_t>(b, lay.split);
     hp.tcur = at<int64_t>(b, lay.tcur);
+    hp.rank = at<nb::BatchRank>(b, lay.rank);
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) {
         b->force_grid_req = 0;
@@ -248,6 +271,8 @@ nbody_status nbody_batch_create(const nbody_config *cfg, int32_t n_clusters, con
     if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int64_t *>(L.off), b->off.data(), b->off.size() * sizeof(int64_t),
                                             hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int32_t *>(L.ord), b->ord.data(), b->ord.size() * sizeof(int32_t),
+                                            hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(const_cast<int32_t *>(L.blk), b->blk.data(), b->blk.size() * sizeof(int32_t),
                                             hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(L.ctr, 0, sizeof(nb::BatchCounters), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(hp.tcur, 0, size_t(n_clusters) * sizeof(int64_t), b->stream);
@@ -450,7 +475,7 @@ nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t 
         return fail(NBODY_E_INVALID, "i_tile must be 0, 64, 128 or 256");
     nb::BatchLaunch &L = b->L;
     L.itile = i_tile > 0 ? i_tile : 64;
-    L.per_wg = per_wg > 0 ? per_wg : 4;
+    L.per_wg = per_wg > 0 ? per_wg : 8;
     b->force_grid_req = force_grid;
     L.force_grid = force_grid > 0 ? force_grid : nb::batch_force_resident(b->cfg.order, b->cfg.precision, L.itile, b->device);
     if (L.force_grid <= 0) return fail(NBODY_E_HIP, "occupancy query of the batched force kernel failed");
@@ -481,9 +506,9 @@ nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *st, int32_t steps
         return fail(NBODY_E_HIP, "hipEventCreate failed");
     }
     const int itiles[3] = {64, 128, 256};
-    const int targets[5] = {1, 2, 4, 8, 16};
+    const int targets[5] = {2, 4, 8, 16, 32};
     double best = -1.0;
-    int best_i = 64, best_t = 16;
+    int best_i = 64, best_t = 8;
     nb::BatchCounters c0, c1;
     for (int it : itiles)
         for (int tg : targets) {
