@@ -273,10 +273,12 @@ def run_batched(args):
     tuned = None
     if args.autotune_steps > 0:
         t0 = time.perf_counter()
+        st0 = B.stats().steps
         B.autotune(args.autotune_steps)
         tuned = B.get_launch()
-        log("[batched] autotune (%d steps per shape): force_grid %d, items per workgroup %d, i_tile %d, %.1f s"
-            % (args.autotune_steps, tuned[0], tuned[1], tuned[2], time.perf_counter() - t0))
+        log("[batched] autotune (every shape timed on the same %d steps, %d batched steps taken): force_grid %d, "
+            "items per workgroup %d, i_tile %d, %.1f s"
+            % (args.autotune_steps, B.stats().steps - st0, tuned[0], tuned[1], tuned[2], time.perf_counter() - t0))
     shape = B.get_launch()
     h = B.to_numpy()   # the common starting state of the three timed runs
     B.capture()
@@ -929,7 +931,8 @@ def main():
     ap.add_argument("--batch-grid", type=int, default=0, help="persistent force workgroups (0 = resident)")
     ap.add_argument("--batch-itile", type=int, default=0, help="active rows per work item, 64 or 256 (0 = default)")
     ap.add_argument("--warm-time", type=float, default=1.0 / 64, help="batched: integrate to this time first")
-    ap.add_argument("--autotune-steps", type=int, default=2, help="batched: steps per autotuned shape (0 = off)")
+    ap.add_argument("--autotune-steps", type=int, default=4,
+                    help="batched: steps on which the autotuner times every shape (0 = off)")
     ap.add_argument("--skip-per-cluster", action="store_true", help="batched: skip the one-context-per-cluster run")
     ap.add_argument("--occupancy-steps", type=int, default=20, help="batched: steps whose active counts are tallied")
     ap.add_argument("--gpus", type=int, default=1)

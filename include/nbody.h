@@ -402,11 +402,13 @@ nbody_status nbody_batch_set_launch(nbody_batch *b, int32_t force_grid, int32_t 
 /* The shape in use (HOST out[3]): force_grid, items_per_wg, i_tile. */
 nbody_status nbody_batch_get_launch(nbody_batch *b, int32_t out[3]);
 
-/* Autotuner: times `steps` batched steps (after one untimed step) for each
- * i_tile in {64, 128, 256} and items_per_wg in {2, 4, 8, 16, 32} with HIP events,
- * and keeps the shape with the most pair interactions per second.  The
- * steps are real: the clusters advance by 15 * (steps + 1) batched steps
- * (fewer where they reach t_end).  Drops a captured graph (capture again). */
+/* Autotuner over `steps` batched steps: before each step, for every i_tile
+ * in {64, 128, 256} and items_per_wg in {2, 4, 8, 16, 32}, plans that step
+ * for the shape and times its force phase (persistent force kernel and split
+ * reduction) once after one untimed pass, with HIP events; then takes the
+ * step (real: the clusters advance by `steps` batched steps, with the shape
+ * in use before the call).  Every shape is timed on the same steps; keeps the
+ * shape with the least total time.  Drops a captured graph (capture again). */
 nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *state, int32_t steps);
 
 /* Message for the last non-OK status returned on this thread. */

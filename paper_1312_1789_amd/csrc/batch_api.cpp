@@ -499,47 +499,88 @@ nbody_status nbody_batch_autotune(nbody_batch *b, nbody_state *st, int32_t steps
     if (s != NBODY_OK) return s;
     if (steps < 1 || steps > 100000) return fail(NBODY_E_INVALID, "steps must be in [1, 100000]");
     drop_graph(b);
+    const nbody_config &c = b->cfg;
+    nb::BatchLaunch &L = b->L;
+    void *rec = b->ws + b->lay.rec;
+    double *F = L.force;
+    const int64_t n = c.n;
+    const int keep_t = L.per_wg, keep_i = L.itile;
+    const int itiles[3] = {64, 128, 256};
+    const int targets[5] = {2, 4, 8, 16, 32};
+    double total_ms[3][5] = {};
+    // planning a step writes the counters, the clusters' times and the live
+    // count: kept aside around each sweep and put back
+    nb::BatchCounters ctr0;
+    int64_t live0 = 0;
+    std::vector<int64_t> tcur0(size_t(b->nc));
+    int64_t *tcur = at<int64_t>(b, b->lay.tcur);
+    char *live_dev = reinterpret_cast<char *>(L.plan) + offsetof(nb::BatchPlan, n_live);
     hipEvent_t e0, e1;
     NB_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return fail(NBODY_E_HIP, "hipEventCreate failed");
     }
-    const int itiles[3] = {64, 128, 256};
-    const int targets[5] = {2, 4, 8, 16, 32};
-    double best = -1.0;
-    int best_i = 64, best_t = 8;
-    nb::BatchCounters c0, c1;
-    for (int it : itiles)
-        for (int tg : targets) {
-            s = nbody_batch_set_launch(b, b->force_grid_req, tg, it);
-            // one untimed step, then `steps` timed ones
-            if (s == NBODY_OK) s = enqueue_step(b, *st);
-            if (s == NBODY_OK && hipMemcpyAsync(&c0, b->L.ctr, sizeof(c0), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
-                s = fail(NBODY_E_HIP, "counter copy failed");
-            if (s == NBODY_OK && hipEventRecord(e0, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
-            for (int r = 0; s == NBODY_OK && r < steps; ++r) s = enqueue_step(b, *st);
-            if (s == NBODY_OK && hipEventRecord(e1, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
-            if (s == NBODY_OK && hipMemcpyAsync(&c1, b->L.ctr, sizeof(c1), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
-                s = fail(NBODY_E_HIP, "counter copy failed");
-            if (s == NBODY_OK) s = sync(b);
-            float ms = 0.0f;
-            if (s == NBODY_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(NBODY_E_HIP, "event timing failed");
-            if (s != NBODY_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return s;
+    for (int k = 0; s == NBODY_OK && k < steps; ++k) {
+        if (hipMemcpyAsync(&ctr0, L.ctr, sizeof(ctr0), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipMemcpyAsync(&live0, live_dev, sizeof(live0), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipMemcpyAsync(tcur0.data(), tcur, tcur0.size() * sizeof(int64_t), hipMemcpyDeviceToHost, b->stream) !=
+                hipSuccess)
+            s = fail(NBODY_E_HIP, "counter copy failed");
+        if (s == NBODY_OK) s = sync(b);
+        bool predicted = false;
+        for (int a = 0; s == NBODY_OK && a < 3; ++a)
+            for (int t = 0; s == NBODY_OK && t < 5; ++t) {
+                s = nbody_batch_set_launch(b, b->force_grid_req, targets[t], itiles[a]);
+                // this step planned for the shape (the active sets and records
+                // do not depend on it); one untimed and one timed force phase
+                if (s == NBODY_OK && nb::batch_schedule(L, *st, 0, c.order, b->stream) != hipSuccess)
+                    s = fail(NBODY_E_HIP, "schedule launch failed");
+                if (s == NBODY_OK && !predicted) {
+                    if (nb::batch_predict(L, *st, c.order, c.precision, rec, b->stream) != hipSuccess)
+                        s = fail(NBODY_E_HIP, "predictor launch failed");
+                    predicted = true;
+                }
+                for (int r = 0; s == NBODY_OK && r < 2; ++r) {
+                    if (r == 1 && hipEventRecord(e0, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
+                    if (s == NBODY_OK && (nb::batch_requeue(L, b->stream) != hipSuccess ||
+                                          nb::batch_force(L, c.order, c.precision, rec, b->stream) != hipSuccess ||
+                                          nb::batch_reduce(L, c.order, F, F + 3 * n, F + 6 * n, F + 9 * n, b->stream) !=
+                                              hipSuccess))
+                        s = fail(NBODY_E_HIP, "force launch failed");
+                }
+                if (s == NBODY_OK && hipEventRecord(e1, b->stream) != hipSuccess) s = fail(NBODY_E_HIP, "event record failed");
+                if (s == NBODY_OK) s = sync(b);
+                float ms = 0.0f;
+                if (s == NBODY_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    s = fail(NBODY_E_HIP, "event timing failed");
+                total_ms[a][t] += double(ms);
             }
-            const double rate = double(c1.interactions - c0.interactions) / std::max(double(ms), 1e-6);
-            if (rate > best) {
-                best = rate;
-                best_i = it;
-                best_t = tg;
-            }
-        }
+        if (s == NBODY_OK &&
+            (hipMemcpyAsync(L.ctr, &ctr0, sizeof(ctr0), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+             hipMemcpyAsync(live_dev, &live0, sizeof(live0), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+             hipMemcpyAsync(tcur, tcur0.data(), tcur0.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->stream) !=
+                 hipSuccess))
+            s = fail(NBODY_E_HIP, "restoring the counters failed");
+        // then the step itself, with the shape in use before the call
+        if (s == NBODY_OK) s = nbody_batch_set_launch(b, b->force_grid_req, keep_t, keep_i);
+        if (s == NBODY_OK) s = enqueue_step(b, *st);
+        if (s == NBODY_OK) s = sync(b);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return nbody_batch_set_launch(b, b->force_grid_req, best_t, best_i);
+    if (s != NBODY_OK) {
+        (void)nbody_batch_set_launch(b, b->force_grid_req, keep_t, keep_i);
+        return s;
+    }
+    int best_a = 0, best_t = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int t = 0; t < 5; ++t)
+            if (total_ms[a][t] < total_ms[best_a][best_t]) {
+                best_a = a;
+                best_t = t;
+            }
+    return nbody_batch_set_launch(b, b->force_grid_req, targets[best_t], itiles[best_a]);
 }
 
 }  // extern "C"
