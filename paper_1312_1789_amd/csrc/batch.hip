@@ -520,6 +520,9 @@ k_b_force(const typename Pol::Rec *__restrict__ rec, int nc, const int32_t *__re
     const ET e2 = ET(eps2);
     const BatchRank *__restrict__ rk = pl->rank;
     const int64_t total = rk[nc - 1].i1;
+    // a step with fewer items than workgroups: the first `total` workgroups
+    // (spread over the XCDs) take them all, the others leave at once
+    if (int64_t(blockIdx.x) >= total) return;
     const int x0 = int(blockIdx.x) % kXcds;
     const int64_t ahead = 2 * ((int64_t(gridDim.x) + kXcds - 1) / kXcds);   // two items per workgroup of an XCD
     for (int v = 0; v < kXcds; ++v) {
