@@ -337,7 +337,7 @@ nbody_status nbody_get_timers(nbody_ctx *ctx, double ms[5] /* host */, int64_t *
  * by one block step of its own (its own t_next and active set), with the
  * same arithmetic as nbody_step.  The launch sequence of a step does not
  * depend on the data (fixed grids; a persistent force kernel takes
- * (cluster, i-tile, j-split) work items from a device queue, largest
+ * (cluster, i-tile, j-split) work items from per-XCD device queues, largest
  * clusters first), so it can be captured once in a HIP graph and replayed.
  * ------------------------------------------------------------------------ */
 typedef struct nbody_batch nbody_batch;

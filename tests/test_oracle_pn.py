@@ -1,5 +1,5 @@
 """Pins of the oracle's post-Newtonian terms between black holes (the paper's
-relativistic corrections for black-hole binaries, Introduction; 1PN and 2.5PN
+relativistic corrections for black-hole binaries, Introduction; 1PN, 2PN and 2.5PN
 two-body terms in harmonic coordinates) against results the physics fixes:
 
 * 2.5PN, circular orbit: the instantaneous power mu v.a equals the
