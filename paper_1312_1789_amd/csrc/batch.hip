@@ -303,8 +303,9 @@ k_b_predict(int64_t n, const int32_t *__restrict__ cid, const int64_t *__restric
 // lane, so one record read from LDS serves two rows) and lane sl of the group
 // takes j0 + sl, j0 + sl + JS, ... .  The JS lanes' sums are folded with a
 // fixed butterfly and lane sl = 0 stores the group's rows.  A tile of `rows`
-// active rows takes the largest JS with 2R >= rows, so a cluster's last,
-// partly filled tile leaves at most half of its lanes idle.
+// active rows takes the largest JS (at most 64 and the tile length) with
+// 2R >= rows, so a cluster's last, partly filled tile leaves at most half of
+// its lanes idle (b_item_rows).
 template <class Pol, int P, int JS, int TILE>
 __device__ __forceinline__ void b_item(const typename Pol::Rec *__restrict__ rec, const int32_t *__restrict__ al,
                                        int64_t na, int64_t row0, int64_t base, int64_t nn, int64_t nh, int64_t j0,
@@ -320,7 +321,6 @@ __device__ __forceinline__ void b_item(const typename Pol::Rec *__restrict__ rec
     constexpr int NV = 3 * (P / 2);
     constexpr int PIECES = int(sizeof(Rec) / 16);       // 16-byte pieces per record
     constexpr int PER_T = (TILE * PIECES + 63) / 64;     // pieces each lane moves per tile
-    constexpr int CH = Pol::kChunk > 0 ? Pol::kChunk / JS : (1 << 30);   // a lane's j per FP32 chunk
     typedef uint4 __attribute__((may_alias)) piece_t;
     const int lane = int(threadIdx.x);
     const int r = lane / JS, sl = lane % JS;
