@@ -308,6 +308,32 @@ def test_batch_autotune_keeps_parity():
         assert st["max"] <= 50 * LOW_TOL[key]
 
 
+def test_batch_autotune_takes_plain_steps():
+    """The shapes the autotuner times leave no trace: after autotune(k) the
+    state equals, bit for bit, that of k plain batched steps with the shape
+    in use before the call (the timed force phases overwrite only scratch;
+    the counters, cluster times and live count the planning writes are put
+    back)."""
+    models = _clusters(990)
+    A = _batch(models, 6, "mixed")
+    A.init()
+    A.autotune(2)
+    B = _batch(models, 6, "mixed")
+    B.init()
+    B.step(2)
+    ha, hb = A.to_numpy(), B.to_numpy()
+    for k in ("x", "v", "t_tick", "level"):
+        np.testing.assert_array_equal(ha[k], hb[k])
+    for da, db in zip(ha["d"], hb["d"]):
+        np.testing.assert_array_equal(da, db)
+    sa, sb = A.stats(), B.stats()
+    assert (sa.steps, sa.sum_n_act, sa.interactions) == (sb.steps, sb.sum_n_act, sb.interactions)
+    la, lb = A.poll(), B.poll()
+    assert la[0] == lb[0] and list(la[1]) == list(lb[1])
+    A.close()
+    B.close()
+
+
 def test_batch_c4_scale():
     """The batched workload at its configured scale: 256 Plummer clusters,
     N_c = round(2^U(10, 16)) (seed 1400, n = 4.25M), 6th order, MIXED, one
