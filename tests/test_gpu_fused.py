@@ -108,7 +108,7 @@ def test_fused_force_parity(block_case, order, precision):
         if precision == "fp64":
             assert st["rms"] <= FP64_TOL["rms"] and st["max"] <= FP64_TOL["max"], (k, st)
         else:
-            assert st["rms"] <= LOW_TOL[k], (k, st)
+            assert st["rms"] <= LOW_TOL[k] and st["max"] <= 10 * LOW_TOL[k], (k, st)
     sim.close()
 
 
